@@ -1,0 +1,272 @@
+"""Pins of the oracle's ROI detection and per-component RLE.
+
+ROI: brute force with numpy's nonzero, rectangles the generator placed itself,
+corner, empty and full images, and the float emptiness readings.
+RLE: the hand-derived RLE1 byte streams in tests/golden, an independent parser
+and decoder written here in plain Python (structure, maximal runs, the raw
+rule, the layout), round trips on adversarial planes, and corrupt streams."""
+import struct
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import read_hex
+
+F = 0xFFFFFFFF
+
+
+# ------------------------------------------------------------------- ROI
+def _np_bbox(mask):
+    ys, xs = np.nonzero(mask)
+    if len(xs) == 0:
+        return (0, 0, 0, 0)
+    return (int(xs.min()), int(ys.min()), int(xs.max() - xs.min() + 1), int(ys.max() - ys.min() + 1))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_roi_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    H, W, P = int(rng.integers(1, 20)), int(rng.integers(1, 20)), 0
+    P = W + int(rng.integers(0, 4))
+    d = np.full((H, P), F, np.uint32)
+    m = rng.random((H, P)) < (0.02 if seed % 2 else 0.3)
+    d[m] = rng.integers(0, F, m.sum(), dtype=np.uint64).astype(np.uint32)
+    assert oracle.roi_detect_depth(d, W, H) == _np_bbox(m[:, :W])
+    c = np.where(m, rng.integers(1, 2 ** 32, (H, P), dtype=np.uint64), 0).astype(np.uint32)
+    assert oracle.roi_detect_rgba8(c, W, H) == _np_bbox(c[:, :W] != 0)
+    f = np.zeros((H, P, 4), np.float32)
+    f[m, int(seed % 4)] = rng.random(m.sum()).astype(np.float32) + 0.5
+    assert oracle.roi_detect_rgbaf(f, W, H) == _np_bbox(m[:, :W])
+
+
+def test_roi_special_images():
+    d = np.full((7, 9), F, np.uint32)
+    assert oracle.roi_detect_depth(d) == (0, 0, 0, 0)
+    d[6, 8] = 0
+    assert oracle.roi_detect_depth(d) == (8, 6, 1, 1)
+    d[0, 0] = F - 1
+    assert oracle.roi_detect_depth(d) == (0, 0, 9, 7)
+    assert oracle.roi_detect_depth(np.zeros((7, 9), np.uint32)) == (0, 0, 9, 7)
+    # float readings: -0.0 is empty, NaN is data
+    f = np.zeros((4, 5, 4), np.float32)
+    f[1, 2, 0] = -0.0
+    assert oracle.roi_detect_rgbaf(f) == (0, 0, 0, 0)
+    f[2, 3, 3] = np.nan
+    assert oracle.roi_detect_rgbaf(f) == (3, 2, 1, 1)
+    h = np.zeros((4, 5, 4), np.float16)
+    h[3, 1, 2] = np.float16(6e-8)  # smallest fp16 subnormal is data
+    assert oracle.roi_detect_rgbaf(h) == (1, 3, 1, 1)
+
+
+def test_roi_of_generated_contributors_is_exact():
+    """The ramp generator knows the rectangle it drew; depth noise stays below
+    the clear value, so detection must return it exactly."""
+    for i in range(6):
+        img = synth.ramp_image(2, i, i, 160, 90, pitch_pad=64)
+        d = synth.as_u32(img.depth)
+        assert oracle.roi_detect_depth(d, 160, 90) == img.true_roi
+
+
+# ------------------------------------------------------------------- RLE
+class Parsed:
+    pass
+
+
+def parse_rle1(s: bytes):
+    """Independent reader of the RLE1 layout (plain Python)."""
+    p = Parsed()
+    magic, x, y, w, h, npl, blk, nb = struct.unpack_from("<IiiiiIII", s, 0)
+    assert magic == 0x31454C52 and blk == 4096
+    p.roi, p.nplanes, p.nblocks = (x, y, w, h), npl, nb
+    npx = w * h
+    assert nb == -(-npx // 4096)
+    boff = struct.unpack_from(f"<{nb}I", s, 32)
+    sizes = struct.unpack_from(f"<{nb * npl}I", s, 32 + 4 * nb)
+    p0 = 32 + 4 * nb * (1 + npl)
+    p0 = (p0 + 15) // 16 * 16
+    assert all(b == 0 for b in s[32 + 4 * nb * (1 + npl):p0])
+    planes = [bytearray() for _ in range(npl)]
+    pos = 0
+    p.tokens = []
+    for b in range(nb):
+        ln = min(4096, npx - 4096 * b)
+        assert boff[b] == pos and pos % 16 == 0
+        q = p0 + pos
+        tot = 0
+        for k in range(npl):
+            sz = sizes[b * npl + k]
+            enc = s[q:q + sz]
+            if sz == ln:
+                planes[k] += enc
+                p.tokens.append(None)
+            else:
+                assert sz % 2 == 0 and 0 < sz < ln
+                toks = [(enc[2 * t] + 1, enc[2 * t + 1]) for t in range(sz // 2)]
+                assert sum(r for r, _ in toks) == ln
+                # the raw rule: tokens only when strictly smaller
+                assert 2 * len(toks) < ln
+                # maximal runs that never cross a multiple of 256 pixels
+                start = 4096 * b
+                for (r, v), nxt in zip(toks, toks[1:] + [None]):
+                    assert start // 256 == (start + r - 1) // 256
+                    if nxt is not None and (start + r) % 256 != 0:
+                        assert nxt[1] != v
+                    start += r
+                for r, v in toks:
+                    planes[k] += bytes([v]) * r
+                p.tokens.append(toks)
+            q += sz
+            tot += sz
+        padded = (tot + 15) // 16 * 16
+        assert all(c == 0 for c in s[p0 + pos + tot:p0 + pos + padded])
+        pos += padded
+    assert len(s) == p0 + pos
+    p.planes = [bytes(pl) for pl in planes]
+    return p
+
+
+def _planes_of(color, depth, roi):
+    x, y, w, h = roi
+    words = [color[y:y + h, x:x + w].reshape(-1)]
+    if depth is not None:
+        words.append(depth[y:y + h, x:x + w].reshape(-1))
+    out = []
+    for wd in words:
+        for k in range(4):
+            out.append(((wd >> (8 * k)) & 0xFF).astype(np.uint8).tobytes())
+    return out
+
+
+def test_golden_stream_of_worked_example():
+    depth = np.array([[5, 5, F, F], [5, 3, F, F], [F, F, F, F], [F, F, 7, F]], np.uint32)
+    color = np.where(depth != F, 0xFF332211, 0).astype(np.uint32)
+    roi = oracle.roi_detect_depth(depth)
+    assert roi == (0, 0, 3, 4)
+    exp = read_hex("rle_A_roi.txt")
+    assert len(exp) == 176
+    got = oracle.rle_compress(color, depth, roi).tobytes()
+    assert got == exp
+    r, c, d = oracle.rle_decompress(np.frombuffer(exp, np.uint8))
+    assert r == roi and (c == color[:, :3]).all() and (d == depth[:, :3]).all()
+    parse_rle1(exp)
+
+
+def test_golden_stream_run_across_256():
+    color = np.full((1, 300), 0x7E7E7E7E, np.uint32)
+    exp = read_hex("rle_run300.txt")
+    got = oracle.rle_compress(color, color.copy(), (0, 0, 300, 1)).tobytes()
+    assert got == exp
+
+
+def test_hand_built_two_block_stream():
+    """4097 pixels of colour 0 and clear depth: block 0 holds 16 runs of 256
+    per plane (32 bytes), block 1 one pixel per plane, stored raw (2 >= 1)."""
+    color = np.zeros((1, 4097), np.uint32)
+    depth = np.full((1, 4097), F, np.uint32)
+    hdr = struct.pack("<IiiiiIII", 0x31454C52, 0, 0, 4097, 1, 8, 4096, 2)
+    boff = struct.pack("<2I", 0, 256)
+    sizes = struct.pack("<16I", *([32] * 8 + [1] * 8))
+    tables = hdr + boff + sizes
+    tables += b"\0" * (112 - len(tables))
+    block0 = b"\xff\x00" * 16 * 4 + b"\xff\xff" * 16 * 4
+    block1 = b"\x00" * 4 + b"\xff" * 4 + b"\0" * 8
+    exp = tables + block0 + block1
+    assert len(exp) == 384
+    assert oracle.rle_compress(color, depth, (0, 0, 4097, 1)).tobytes() == exp
+
+
+def _adversarial_images(rng, H, W):
+    c = np.zeros((H, W), np.uint32)
+    d = np.full((H, W), F, np.uint32)
+    flat = c.reshape(-1)
+    dflat = d.reshape(-1)
+    n = flat.size
+    # runs of 255, 256, 257 and 1, noise, and a long constant tail
+    pos = 0
+    for run in [255, 256, 257, 1, 1, 2, 511, 513, 4095, 4096, 4097]:
+        if pos >= n:
+            break
+        flat[pos:pos + run] = rng.integers(0, 2 ** 32, dtype=np.uint64)
+        dflat[pos:pos + run] = rng.integers(0, 2 ** 32, dtype=np.uint64)
+        pos = min(n, pos + run)
+    k = min(n, pos + 3000)
+    flat[pos:k] = rng.integers(0, 2 ** 32, k - pos, dtype=np.uint64).astype(np.uint32)
+    dflat[pos:k] = rng.integers(0, 2 ** 32, k - pos, dtype=np.uint64).astype(np.uint32)
+    return c, d
+
+
+@pytest.mark.parametrize("shape,roi", [
+    ((1, 1), (0, 0, 1, 1)),
+    ((130, 150), (0, 0, 150, 130)),
+    ((130, 150), (7, 3, 129, 101)),
+    ((64, 128), (0, 0, 128, 32)),    # exactly one block
+    ((65, 64), (0, 0, 64, 65)),      # one block + 64 pixels
+    ((20, 30), (5, 5, 0, 7)),        # empty ROI
+])
+def test_round_trip_and_structure(shape, roi):
+    rng = np.random.default_rng(sum(shape) + sum(roi))
+    c, d = _adversarial_images(rng, *shape)
+    for depth in (d, None):
+        s = oracle.rle_compress(c, depth, roi)
+        assert s.size <= oracle.rle_max_size(roi[2], roi[3], 8 if depth is not None else 4)
+        p = parse_rle1(s.tobytes())
+        assert p.roi == roi
+        assert p.planes == _planes_of(c, depth, roi)
+        r, c2, d2 = oracle.rle_decompress(s)
+        x, y, w, h = roi
+        assert r == roi
+        assert (c2 == c[y:y + h, x:x + w]).all()
+        if depth is not None:
+            assert (d2 == d[y:y + h, x:x + w]).all()
+        else:
+            assert d2 is None
+
+
+def test_generated_ramp_contributor_round_trip():
+    img = synth.ramp_image(2, 3, 3, 320, 180, pitch_pad=64)
+    c, d = synth.as_u32(img.color), synth.as_u32(img.depth)
+    roi = oracle.roi_detect_depth(d, 320, 180)
+    s = oracle.rle_compress(c, d, roi)
+    p = parse_rle1(s.tobytes())
+    assert p.planes == _planes_of(c, d, roi)
+    # the smooth colour gradients and clear-free interior compress; the noisy
+    # low depth byte is stored raw
+    assert s.size < 8 * roi[2] * roi[3]
+    assert all(t is None for t in p.tokens[4::8])
+
+
+def test_corrupt_streams_are_rejected():
+    depth = np.array([[5, 5, F], [5, 3, F], [F, F, F], [F, F, 7]], np.uint32)
+    color = np.where(depth != F, 0xFF332211, 0).astype(np.uint32)
+    good = oracle.rle_compress(color, depth, (0, 0, 3, 4))
+    oracle.rle_decompress(good)
+
+    def bad(mut):
+        s = good.copy()
+        mut(s)
+        with pytest.raises(oracle.CorruptStream):
+            oracle.rle_decompress(s)
+
+    bad(lambda s: s.__setitem__(0, 0x53))                     # magic
+    bad(lambda s: s.__setitem__(20, 5))                       # nplanes
+    bad(lambda s: s.__setitem__(25, 0x20))                    # block size
+    bad(lambda s: s.__setitem__(28, 2))                       # nblocks
+    bad(lambda s: s.__setitem__(32, 16))                      # block offset
+    bad(lambda s: s.__setitem__(36, 11))                      # odd token size
+    bad(lambda s: s.__setitem__(36, 13))                      # size > block length
+    bad(lambda s: s.__setitem__(80, 0x05))                    # runs overflow block
+    bad(lambda s: s.__setitem__(80, 0x00))                    # runs short of block
+    with pytest.raises(oracle.CorruptStream):
+        oracle.rle_decompress(good[:100])                     # truncated
+    with pytest.raises(oracle.CorruptStream):
+        oracle.rle_decompress(good[:20])
+
+
+def test_max_size_formula():
+    for w, h, npl in [(0, 0, 8), (1, 1, 8), (4096, 1, 4), (4097, 1, 8), (1920, 1080, 8)]:
+        nb = -(-w * h // 4096)
+        p0 = (32 + 4 * nb * (1 + npl) + 15) // 16 * 16
+        body = sum(((min(4096, w * h - 4096 * b) * npl) + 15) // 16 * 16 for b in range(nb))
+        assert oracle.rle_max_size(w, h, npl) == p0 + body
