@@ -1,0 +1,436 @@
+"""Benchmark of the sort-last compositing path on one MI355X.
+
+One step = the whole hot path over one frame of the 16-contributor workload
+(16 x 1920x1080 RGBA8 + uint32 depth framebuffers, each holding a ~30%
+region of interest with a smooth depth ramp plus noise):
+    ROI detection of the 16 framebuffers
+ -> per-component RLE compression of the 16 ROIs
+ -> decompression of the 16 streams
+ -> depth compositing of the 16 ROI blocks into 1920x1080 with the
+    binary-swap schedule over 16 owners (tiles of 480x270).
+Inputs are resident in HBM before timing starts; the step rotates over
+several copies of every buffer so that the 256 MB Infinity Cache cannot
+serve a step from the previous one.
+
+Prints one JSON line: Mpixel/s of composited input (the sum of the ROI areas
+supplied per frame), the roofline of the dominant kernel (algorithmic bytes
+over its event-timed average duration), and the oracle timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+import paper_1902_08755_amd as cmp  # noqa: E402
+import synth  # noqa: E402
+
+PEAK_HBM_GBPS = 8000.0
+METRIC = "composited input Mpixel/s and achieved HBM GB/s (% peak), plain vs batched/backward"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+class Frame:
+    """One copy of every buffer of the pipeline."""
+
+    def __init__(self, wl, dev):
+        self.images = wl.images
+        self.roi = torch.zeros((16, 4), dtype=torch.int32, device=dev)
+        self.rle = cmp.RleBatch(self.images, roi_dev=self.roi)
+        W, H = wl.viewport[2], wl.viewport[3]
+        self.blocks = [cmp.Image(torch.zeros((H, W), dtype=torch.int32, device=dev),
+                                 torch.zeros((H, W), dtype=torch.int32, device=dev), (0, 0, W, H))
+                       for _ in self.images]
+        self.roi_dec = torch.zeros((16, 4), dtype=torch.int32, device=dev)
+        self.status = torch.zeros(16, dtype=torch.int32, device=dev)
+        self.out_c = torch.zeros((H, W), dtype=torch.int32, device=dev)
+        self.out_d = torch.zeros((H, W), dtype=torch.int32, device=dev)
+        self.viewport = wl.viewport
+        # pre-marshalled C arguments: the timed loop only calls the library
+        L = cmp.lib()
+        self.img_arr = cmp._images(self.images, "u32")
+        self.roi_ws = torch.zeros(L.cmp_roi_workspace_size(self.img_arr, 16), dtype=torch.uint8,
+                                  device=dev)
+        self.dec_in = (ctypes.c_void_p * 16)(*[o.data_ptr() for o in self.rle.outs])
+        self.dec_bytes = (ctypes.c_uint64 * 16)(*[o.numel() for o in self.rle.outs])
+        self.dec_out = cmp._images(self.blocks, "u32")
+        self.comp_in = cmp._images(self.blocks, "u32")
+
+    def stage(self, k, s):
+        L = cmp.lib()
+        if k == 0:
+            st = L.cmp_roi_detect(self.img_arr, 16, cmp.RGBA8, self.roi.data_ptr(),
+                                  self.roi_ws.data_ptr(), self.roi_ws.numel(), s)
+        elif k == 1:
+            r = self.rle
+            st = L.cmp_rle_compress(r.arr, 16, cmp.RGBA8, self.roi.data_ptr(), r.out_ptrs,
+                                    r.cap_arr, r.sizes.data_ptr(), r.status.data_ptr(),
+                                    r.ws.data_ptr(), r.ws.numel(), s)
+        elif k == 2:
+            st = L.cmp_rle_decompress(self.dec_in, self.dec_bytes, 16, self.dec_out,
+                                      self.roi_dec.data_ptr(), self.status.data_ptr(), s)
+        else:
+            st = L.cmp_composite_depth(self.comp_in, 16, self.roi_dec.data_ptr(),
+                                       cmp._rect(self.viewport), self.out_c.data_ptr(),
+                                       self.out_d.data_ptr(), self.out_c.stride(0),
+                                       cmp.Schedule(cmp.BINARY_SWAP, 16), cmp.Tile(0, 0), s)
+        if st != 0:
+            raise cmp.CmpError(st, f"stage {k}", L.cmp_last_error().decode())
+
+
+STAGES = ["roi_detect", "rle_compress", "rle_decompress", "composite_depth"]
+
+
+def algorithmic_bytes(frame, rois, stream_sizes):
+    """Bytes each stage must move (reads + writes), from the frame's ROIs."""
+    W, H = frame.viewport[2], frame.viewport[3]
+    roi_px = sum(w * h for _, _, w, h in rois)
+    cover = np.zeros((H, W), np.int32)
+    for x, y, w, h in rois:
+        cover[y:y + h, x:x + w] += 1
+    covered = int((cover > 0).sum())
+    comp = int(stream_sizes.sum())
+    return {
+        "roi_detect": 16 * W * H * 4 + 16 * 16,
+        "rle_compress": 8 * roi_px + comp,
+        "rle_decompress": comp + 8 * roi_px,
+        # depth of every covering contributor, the winner's colour, and the
+        # output colour + depth
+        "composite_depth": 4 * int(cover.sum()) + 4 * covered + 8 * W * H,
+    }, roi_px
+
+
+def time_stages(frames, steps, warmup, s_obj):
+    s = s_obj.cuda_stream
+    nf = len(frames)
+    for i in range(warmup):
+        f = frames[i % nf]
+        for k in range(4):
+            f.stage(k, s)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record(s_obj)
+    for i in range(steps):
+        f = frames[i % nf]
+        for k in range(4):
+            ev[i][k].record(s_obj)
+            f.stage(k, s)
+        ev[i][4].record(s_obj)
+    t1.record(s_obj)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t0.elapsed_time(t1)
+    per = np.array([[ev[i][k].elapsed_time(ev[i][k + 1]) for k in range(4)] for i in range(steps)])
+    return total_ms, wall, per
+
+
+def time_graph(frames, steps, s_obj):
+    """The same steps captured as HIP graphs (one per frame copy) and replayed."""
+    graphs = []
+    for f in frames:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s_obj):
+            for k in range(4):
+                f.stage(k, s_obj.cuda_stream)
+        graphs.append(g)
+    torch.cuda.synchronize()
+    for g in graphs:
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for i in range(steps):
+        graphs[i % len(graphs)].replay()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1)
+
+
+def cpu_baseline(frame_host, budget_s=25.0):
+    """The oracle chain of one full frame on the host (single thread)."""
+    import oracle
+    colors, depths, viewport = frame_host
+    times = []
+    t_start = time.perf_counter()
+    while len(times) < 3 and (time.perf_counter() - t_start) < budget_s:
+        t = time.perf_counter()
+        rois = [oracle.roi_detect_depth(d) for d in depths]
+        crops_c, crops_d = [], []
+        for c, d, r in zip(colors, depths, rois):
+            s = oracle.rle_compress(c, d, r)
+            _, cc, dd = oracle.rle_decompress(s)
+            crops_c.append(cc)
+            crops_d.append(dd)
+        oracle.composite_depth(crops_c, crops_d, rois, viewport)
+        times.append(time.perf_counter() - t)
+    return float(np.median(times)), len(times), rois
+
+
+# ------------------------------------------------------------------ extras
+def bench_over(dev, dtype, reps=10):
+    ow = synth.over_bricks(seed=3, n=64, W=3840, H=2160, device=dev, dtype=dtype)
+    out = torch.empty((2160, 3840, 4), dtype=torch.float32, device=dev)
+    for _ in range(2):
+        cmp.composite_over(ow.layers, ow.order, ow.viewport, out=out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        cmp.composite_over(ow.layers, ow.order, ow.viewport, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    esz = 16 if dtype == torch.float32 else 8
+    nbytes = 64 * 3840 * 2160 * esz + 3840 * 2160 * 16
+    del ow, out
+    torch.cuda.empty_cache()
+    return {"ms": ms, "Mpx_per_s": 64 * 3840 * 2160 / ms / 1e3, "GBps": nbytes / ms / 1e6,
+            "hbm_frac": nbytes / ms / 1e6 / PEAK_HBM_GBPS}
+
+
+def bench_backward(dev, reps=10):
+    ow = synth.over_bricks(seed=4, n=32, W=1024, H=1024, device=dev, with_target=True)
+    imgs = ow.layers
+    out = torch.empty((1024, 1024, 4), dtype=torch.float32, device=dev)
+    grads = [torch.empty((1024, 1024, 4), dtype=torch.float32, device=dev) for _ in range(32)]
+    G = torch.randn((1024, 1024, 4), dtype=torch.float32, device=dev)
+
+    def fwd():
+        cmp.composite_over(imgs, ow.order, ow.viewport, out=out)
+
+    def bwd():
+        cmp.composite_over_backward(imgs, ow.order, ow.viewport, G, grads=grads)
+
+    res = {}
+    px = 1024 * 1024
+    for name, fn, nbytes in [("forward", fwd, px * (32 * 16 + 16)),
+                             ("backward", bwd, px * (32 * 16 + 16 + 32 * 16)),
+                             ("forward_backward", lambda: (fwd(), bwd()), px * (2 * 32 * 16 + 32 + 32 * 16))]:
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = {"ms": ms, "Mpx_per_s": 32 * px / ms / 1e3, "GBps": nbytes / ms / 1e6,
+                     "hbm_frac": nbytes / ms / 1e6 / PEAK_HBM_GBPS}
+    return res
+
+
+def bench_batch(dev, reps=5, tune_path=None):
+    jobs = synth.batch_jobs(seed=5, njobs=256, device=dev)
+    outs, keep = [], []
+    arr = (cmp.CJob * len(jobs))()
+    in_px, nbytes = 0, 0
+    for k, job in enumerate(jobs):
+        wl = job.work
+        _, _, w, h = wl.viewport
+        if job.kind == "depth":
+            oc = torch.empty((h, w), dtype=torch.int32, device=dev)
+            od = torch.empty((h, w), dtype=torch.int32, device=dev)
+            imgs = cmp._images(wl.images, "u32")
+            arr[k] = cmp.CJob(0, cmp.RGBA8, len(wl.images), imgs, None, cmp._rect(wl.viewport),
+                              oc.data_ptr(), od.data_ptr(), w)
+            outs.append((oc, od))
+            keep.append(imgs)
+            cover = sum(r[2] * r[3] for r in (i.roi for i in wl.images))
+            covered = min(w * h, cover)
+            nbytes += 4 * cover + 4 * covered + 8 * w * h
+            in_px += cover
+        else:
+            o = torch.empty((h, w, 4), dtype=torch.float32, device=dev)
+            imgs = cmp._images(wl.layers, "rgba")
+            order = (ctypes.c_int32 * len(wl.order))(*wl.order)
+            arr[k] = cmp.CJob(1, cmp.RGBA32F, len(wl.layers), imgs, order, cmp._rect(wl.viewport),
+                              o.data_ptr(), None, w)
+            outs.append(o)
+            keep += [imgs, order]
+            cover = sum(l.roi[2] * l.roi[3] for l in wl.layers)
+            nbytes += 16 * cover + 16 * w * h
+            in_px += cover
+    L = cmp.lib()
+    s = torch.cuda.current_stream()
+    if tune_path:
+        st = L.cmp_autotune(arr, len(jobs), tune_path.encode(), 3, s.cuda_stream)
+        if st != 0:
+            raise cmp.CmpError(st, "cmp_autotune", L.cmp_last_error().decode())
+    plan = ctypes.c_void_p()
+    st = L.cmp_batch_plan_create(arr, len(jobs), tune_path.encode() if tune_path else None,
+                                 ctypes.byref(plan))
+    if st != 0:
+        raise cmp.CmpError(st, "cmp_batch_plan_create", L.cmp_last_error().decode())
+    ws = torch.zeros(L.cmp_batch_workspace_size(plan) + 64, dtype=torch.uint8, device=dev)
+    L.cmp_batch_upload(plan, ws.data_ptr(), ws.numel(), s.cuda_stream)
+    torch.cuda.synchronize()
+    items, wgs = ctypes.c_int64(), ctypes.c_int32()
+    L.cmp_batch_info(plan, ctypes.byref(items), ctypes.byref(wgs))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        L.cmp_batch_run(plan, ws.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    res = {}
+    for name, fn in [("persistent_graph", lambda: g.replay()),
+                     ("persistent", lambda: L.cmp_batch_run(plan, ws.data_ptr(), s.cuda_stream)),
+                     ("plain_launches", lambda: L.cmp_batch_run_plain(plan, s.cuda_stream))]:
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = {"ms": ms, "Mpx_per_s": in_px / ms / 1e3, "GBps": nbytes / ms / 1e6,
+                     "hbm_frac": nbytes / ms / 1e6 / PEAK_HBM_GBPS}
+    res["jobs"] = len(jobs)
+    res["work_items"] = int(items.value)
+    res["workgroups"] = int(wgs.value)
+    res["input_Mpx"] = in_px / 1e6
+    res["algorithmic_GB"] = nbytes / 1e9
+    L.cmp_batch_plan_destroy(plan)
+    del keep, outs
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--copies", type=int, default=4, help="buffer copies rotated per step")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", default="", help="profile helper: run only this stage repeatedly")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+              "(the multi-GPU design is described, not run)", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log("generating 16 x 1920x1080 contributors")
+    frames = []
+    for c in range(args.copies):
+        wl = synth.depth_ramps_full(seed=2, n=16, W=1920, H=1080, device=dev)
+        frames.append(Frame(wl, dev))
+    s_obj = torch.cuda.current_stream()
+    # one checked pass: ROIs and stream sizes for the byte counts
+    for k in range(4):
+        frames[0].stage(k, s_obj.cuda_stream)
+    torch.cuda.synchronize()
+    rois = [tuple(r) for r in frames[0].roi.cpu().tolist()]
+    assert rois == [im.true_roi for im in frames[0].images], "ROI detection mismatch"
+    assert int(frames[0].status.abs().sum()) == 0 and int(frames[0].rle.status.abs().sum()) == 0
+    sizes = frames[0].rle.sizes.cpu().numpy()
+    abytes, roi_px = algorithmic_bytes(frames[0], rois, sizes)
+
+    if args.only:
+        k = STAGES.index(args.only)
+        for i in range(args.steps):
+            frames[i % len(frames)].stage(k, s_obj.cuda_stream)
+        torch.cuda.synchronize()
+        log(f"ran {args.only} {args.steps} times")
+        return
+
+    log(f"timing {args.steps} steps after {args.warmup} warmup")
+    total_ms, wall, per = time_stages(frames, args.steps, args.warmup, s_obj)
+    ms_step = total_ms / args.steps
+    stage_ms = per.mean(axis=0)
+    stages = {}
+    for k, name in enumerate(STAGES):
+        stages[name] = {"us": float(stage_ms[k] * 1e3), "bytes": int(abytes[name]),
+                        "GBps": float(abytes[name] / stage_ms[k] / 1e6)}
+    dom = max(STAGES, key=lambda n: stages[n]["us"])
+    graph_ms = time_graph(frames, args.steps, s_obj) / args.steps
+    step_bytes = sum(abytes.values())
+    achieved = stages[dom]["GBps"]
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        try:
+            t = json.load(open(tpath))
+            if t.get("kernel_stage") == dom and t.get("source_hash") == _source_hash():
+                traffic = t.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    result = {
+        "metric": METRIC,
+        "value": roi_px / (ms_step * 1e3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "sort-last depth pipeline: roi_detect + per-component RLE "
+                               "compress/decompress + depth compositing",
+                   "contributors": 16, "width": 1920, "height": 1080,
+                   "roi_area_fraction": "0.25-0.35", "schedule": "binary_swap(16)",
+                   "composited_input_px_per_step": roi_px, "buffer_copies": args.copies},
+        "hbm_GBps_step": step_bytes / ms_step / 1e6,
+        "hbm_frac_step": step_bytes / ms_step / 1e6 / PEAK_HBM_GBPS,
+        "graph_replay_ms_per_step": graph_ms,
+        "stages": stages,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS, "traffic": traffic},
+        "wall_s_timed": wall,
+    }
+    if not args.no_extras:
+        log("extras: over 64x3840x2160 fp32/fp16, backward 32x1024x1024, batch of 256 jobs")
+        ex = {}
+        ex["over_fp32_64x3840x2160"] = bench_over(dev, torch.float32)
+        ex["over_fp16_64x3840x2160"] = bench_over(dev, torch.float16)
+        ex["over_grad_32x1024x1024"] = bench_backward(dev)
+        ex["batch_256_jobs"] = bench_batch(dev, tune_path=os.path.join(
+            os.environ.get("TMPDIR", "/tmp"), "cmp_tune_cache.txt"))
+        result["extras"] = ex
+    if not args.no_cpu:
+        log("cpu baseline: the oracle chain on one full frame")
+        f = frames[0]
+        host = ([synth.as_u32(im.color) for im in f.images], [synth.as_u32(im.depth) for im in f.images],
+                f.viewport)
+        t, reps, _ = cpu_baseline(host)
+        result["cpu_baseline"] = {"value": roi_px / (t * 1e6), "unit": "Mpixel/s", "cores": 1,
+                                  "kind": "oracle",
+                                  "sample": f"one full frame (16 x 1920x1080) of the same pipeline, "
+                                            f"median of {reps} runs, {t:.2f} s each"}
+    print(json.dumps(result), flush=True)
+
+
+def _source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1902_08755_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,308 @@
+/*
+ * cmp.h - sort-last image compositing on one MI355X (gfx950).
+ *
+ * The data-parallel hot path of sort-last parallel rendering as described in
+ * S. Eilemann, "Parallel Rendering and Large Data Visualization" (thesis,
+ * 2019), chapter 5 "Compositing": depth-sorted and ordered (alpha) sort-last
+ * compositing of many contributors' partial framebuffers, automatic region of
+ * interest (ROI) detection, and per-component run-length encoding (RLE) of
+ * pixel data; plus the adjoint of ordered compositing and a batched,
+ * persistent launch of many uneven compositing jobs.
+ *
+ * Plain C ABI. Every pointer documented as "device" is HIP device memory on
+ * the current device; every "host" pointer is ordinary host memory that is
+ * only read during the call. `stream` is a hipStream_t (NULL = the null
+ * stream). All calls are stream-ordered and asynchronous: a CMP_OK return
+ * means the work is enqueued. Arguments are validated on the host before
+ * anything is enqueued, so an error return means nothing was launched;
+ * cmp_last_error() then describes the problem. Apart from the opaque batch
+ * plan (host memory) the library never allocates: scratch memory is the
+ * caller's "workspace", sized by the *_workspace_size functions.
+ *
+ * Conventions (the thesis fixes none of these; they are this library's):
+ *  - Buffers are row-major, row 0 first in memory; pitches count pixels.
+ *  - cmp_rect {x, y, w, h} is the half-open [x, x+w) x [y, y+h); an empty
+ *    rectangle has w == 0 or h == 0.
+ *  - RGBA8 pixels are little-endian uint32 words with bytes R, G, B, A.
+ *  - Depth is uint32, smaller is nearer, 0xFFFFFFFF is the clear depth.
+ *  - Float layers hold premultiplied RGBA, alpha in channel 3.
+ *  - A contributor's `roi` places its w x h block of pixels at (roi.x, roi.y)
+ *    in destination pixel space (Section 5.3, Region of Interest: the ROI is
+ *    sent with the pixels and used to place them on the input frame).
+ */
+#ifndef CMP_H
+#define CMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cmp_status;
+#define CMP_OK            0
+#define CMP_EINVAL       -1   /* an argument is invalid                        */
+#define CMP_ENOSPC       -2   /* an output or workspace is too small           */
+#define CMP_EHIP         -3   /* the HIP runtime reported an error             */
+#define CMP_EUNSUPPORTED -4   /* a valid request this build does not handle    */
+#define CMP_ECORRUPT     -5   /* an RLE stream is malformed (device status)    */
+#define CMP_ETIMEOUT     -6   /* a bounded device-side wait gave up (status)   */
+
+typedef int32_t cmp_format;
+#define CMP_RGBA8   0   /* uint32 per pixel                                  */
+#define CMP_RGBA32F 1   /* 4 x float per pixel (16 bytes)                    */
+#define CMP_RGBA16F 2   /* 4 x IEEE half per pixel (8 bytes)                 */
+
+typedef struct { int32_t x, y, w, h; } cmp_rect;
+
+/*
+ * Parallel compositing schedule (Section 5.2.2, Direct Send and Binary Swap).
+ * On one GPU the P "owners" are tile assignments inside the launch:
+ *   CMP_SCHED_SEQ          one region, the whole viewport.
+ *   CMP_SCHED_DIRECT_SEND  P row strips; strip k covers the rows
+ *                          [floor(k H / P), floor((k+1) H / P)).
+ *   CMP_SCHED_BINARY_SWAP  P a power of two; log2 P rounds each halve every
+ *                          region along its longer side (rows on a tie; the
+ *                          first half is floor(len / 2) long). For ordered
+ *                          compositing, the back-to-front list is cut into P
+ *                          contiguous groups, group g = positions
+ *                          [floor(g n / P), floor((g+1) n / P)), and the group
+ *                          composites are merged pairwise in the binary tree
+ *                          of the exchange rounds. For depth compositing the
+ *                          merge order cannot change the result (see
+ *                          cmp_composite_depth), so the schedule only decides
+ *                          the tiles.
+ * owners (P) is 1..64.
+ */
+#define CMP_SCHED_SEQ          0
+#define CMP_SCHED_DIRECT_SEND  1
+#define CMP_SCHED_BINARY_SWAP  2
+typedef struct { int32_t kind; int32_t owners; } cmp_schedule;
+
+/* The regions a schedule assigns to its owners over `viewport`, in owner
+ * order, empty regions left out; writes at most `max` rectangles to `out`
+ * (host) and returns how many there are, or a negative cmp_status. Host-only. */
+int32_t cmp_schedule_regions(cmp_schedule sched, cmp_rect viewport, cmp_rect* out, int32_t max);
+
+/* Workgroup tile in destination pixels; {0, 0} picks the default. tile_w must
+ * be a multiple of 4 for depth compositing. The tile never changes results. */
+typedef struct { int32_t w, h; } cmp_tile;
+
+/* One contributor image or layer. */
+typedef struct {
+  const void*     color;  /* device; RGBA8 | RGBA32F | RGBA16F per the call  */
+  const uint32_t* depth;  /* device uint32 depth, or NULL                     */
+  int64_t         pitch;  /* row pitch in pixels, >= roi.w                    */
+  cmp_rect        roi;    /* placement in destination pixels (w x h block)   */
+} cmp_image;
+
+const char* cmp_version(void);
+const char* cmp_status_string(cmp_status s);
+/* Text of the last host-side error on the calling thread ("" if none). */
+const char* cmp_last_error(void);
+
+/*
+ * Depth-sorted sort-last compositing.
+ * Section 5.2.1 (Spatial and Depth-Sorted Sort-Last Compositing): every final
+ * pixel takes the colour of the source with the front-most depth.
+ *   For each destination pixel p in `viewport`, over the contributors i whose
+ *   placement covers p, pick the smallest (depth, i) pair; the clear depth
+ *   0xFFFFFFFF never wins. out_color = the winner's colour, or 0 if none;
+ *   out_depth = the winner's depth, or 0xFFFFFFFF if none.
+ * Ties go to the lower index, which makes the result independent of the
+ * order in which frames are combined (Section 5.6, Out-of-Order Assembly).
+ *   in[n]      host array; color = RGBA8 (uint32), depth required.
+ *   roi_dev    NULL, or device int32[n][4] (x, y, w, h) placements that
+ *              replace in[i].roi.x/y/w/h at run time (e.g. ROIs detected on
+ *              the device). in[i].roi.w/h then bound the buffer: a device
+ *              w or h beyond them is clamped, and negative sizes are empty.
+ *   out_color  device uint32, viewport.w x viewport.h, pitch out_pitch.
+ *   out_depth  device uint32 or NULL (same pitch). Required when n > 48.
+ * n == 0 writes the background. Errors: CMP_EINVAL (n < 0, NULL buffers,
+ * negative sizes, pitch < width, bad schedule or tile), CMP_EHIP.
+ */
+cmp_status cmp_composite_depth(const cmp_image* in, int32_t n, const int32_t* roi_dev,
+                               cmp_rect viewport, uint32_t* out_color, uint32_t* out_depth,
+                               int64_t out_pitch, cmp_schedule sched, cmp_tile tile,
+                               void* stream);
+
+/*
+ * Ordered (spatial) sort-last compositing with alpha blending.
+ * Section 5.2.1: the partial images of convex regions are sorted by depth and
+ * blended in order; ordering is the application's part (Section 3.6,
+ * Compositing: ordered compositing reorders the input frames).
+ *   out(p) = fold over j = 0..n-1 of  acc <- L + (1 - L.alpha) * acc
+ * with L = layer order_b2f[j] at p (transparent outside its placement),
+ * starting from acc = 0; i.e. Porter-Duff "over" of premultiplied colour,
+ * back to front. Arithmetic: FP32 fused multiply-add per channel, FP32
+ * accumulation for RGBA32F and RGBA16F storage.
+ *   in[n]      host array; color = RGBA32F or RGBA16F (fmt), depth unused.
+ *   order_b2f  host int32[n], a permutation of 0..n-1, back to front.
+ *   out_rgba   device float[viewport.h][out_pitch][4].
+ * CMP_SCHED_SEQ and CMP_SCHED_DIRECT_SEND give identical bits; BINARY_SWAP
+ * evaluates the merge tree described above (n <= 64 for it).
+ * Errors: CMP_EINVAL (also a non-permutation order), CMP_EUNSUPPORTED, CMP_EHIP.
+ */
+cmp_status cmp_composite_over(const cmp_image* in, int32_t n, cmp_format fmt,
+                              const int32_t* order_b2f, cmp_rect viewport, float* out_rgba,
+                              int64_t out_pitch, cmp_schedule sched, cmp_tile tile,
+                              void* stream);
+
+/*
+ * Adjoint of cmp_composite_over (SEQ order). The thesis has no backward pass;
+ * this differentiates the forward operation above.
+ * With the layers that cover p in front-to-back order i = 0 (nearest) ..,
+ * T_0 = 1, T_{i+1} = T_i (1 - a_i), and S_i the composite of layers i and
+ * everything behind it (S_end = 0), out = (front part) + T_i S_i, so for
+ * G = grad_out(p):
+ *   grad L_i[k] = G_k T_i,      grad a_i += -T_i * sum_m G_m S_{i+1}[m].
+ * T and S are recomputed per pixel (never stored to memory); the recurrences
+ * run in FP64 and the results are rounded once to FP32.
+ *   grad_out       device float[viewport.h][grad_pitch][4].
+ *   grad_layers    host array of n device float RGBA pointers; layer i's
+ *                  gradient has in[i].roi.w x in[i].roi.h pixels with pitch
+ *                  grad_pitch_layers[i] (host int64[n]) and is fully written
+ *                  (zero where the layer does not reach the viewport).
+ * n <= 64. Errors: CMP_EINVAL, CMP_EUNSUPPORTED, CMP_EHIP.
+ */
+cmp_status cmp_composite_over_backward(const cmp_image* in, int32_t n, cmp_format fmt,
+                                       const int32_t* order_b2f, cmp_rect viewport,
+                                       const float* grad_out, int64_t grad_pitch,
+                                       float* const* grad_layers,
+                                       const int64_t* grad_pitch_layers, void* stream);
+
+/*
+ * Automatic ROI detection: the 2D bounding box of the pixels that hold data
+ * (Section 5.3, Region of Interest: the ROI encloses the rendered data and can
+ * be found by analysing the framebuffer).
+ *   imgs[i] is an image of imgs[i].roi.w x imgs[i].roi.h pixels (roi.x/y are
+ *   ignored). A pixel holds data when: fmt CMP_RGBA8 with depth != NULL:
+ *   depth != 0xFFFFFFFF; CMP_RGBA8 without depth: the colour word != 0;
+ *   CMP_RGBA32F / CMP_RGBA16F: any channel != 0.0 (-0.0 is empty, NaN is data).
+ *   roi_out_dev  device int32[n][4]: image-local (x, y, w, h); an image
+ *                without data gives (0, 0, 0, 0).
+ *   workspace    device, >= cmp_roi_workspace_size(imgs, n) bytes, zero-filled
+ *                before its first use; every call leaves it zeroed again.
+ * Calls that share a workspace must not overlap. n <= 64.
+ * Errors: CMP_EINVAL, CMP_ENOSPC (workspace), CMP_EHIP.
+ */
+size_t     cmp_roi_workspace_size(const cmp_image* imgs, int32_t n);
+cmp_status cmp_roi_detect(const cmp_image* imgs, int32_t n, cmp_format fmt, int32_t* roi_out_dev,
+                          void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Per-component run-length encoding (Section 5.5.1, Enhanced RLE Compression:
+ * one RLE stream per component of the pixel, and the image decomposed into
+ * sub-images that are compressed in parallel). Stream format "RLE1"; all
+ * integers little-endian uint32:
+ *   header  magic 0x31454C52, roi.x, roi.y, roi.w, roi.h, nplanes, 4096,
+ *           nblocks = ceil(roi.w roi.h / 4096)
+ *   boff[nblocks]           payload offset of block b (multiple of 16)
+ *   size[nblocks][nplanes]  encoded bytes of (block b, plane k)
+ *   zero bytes to a multiple of 16; then the payload: per block, its planes'
+ *   encodings back to back, zero-padded to a multiple of 16 bytes.
+ * Planes: byte k of the pixel record, which is the RGBA8 word (planes 0..3,
+ * R G B A) followed, when a depth buffer is given, by the depth word (planes
+ * 4..7, least significant byte first). Pixels are taken row-major over the
+ * ROI; block b covers pixels [4096 b, 4096 b + len_b). A plane of a block is
+ * its maximal runs of equal bytes that do not cross a multiple of 256 pixels,
+ * each stored as (run length - 1, value), when 2 * runs < len_b, and its
+ * len_b raw bytes otherwise (size == len_b marks raw).
+ */
+size_t cmp_rle_max_size(int32_t w, int32_t h, int32_t nplanes);
+
+/*
+ * Compress n images (fmt CMP_RGBA8; 8 planes when imgs[i].depth != NULL,
+ * else 4) in one launch.
+ *   imgs[i]       image of imgs[i].roi.w x imgs[i].roi.h pixels (x/y ignored).
+ *   roi_dev       NULL (whole images) or device int32[n][4] image-local ROIs,
+ *                 e.g. the output of cmp_roi_detect; clamped to the image.
+ *   out           host array of n device pointers, 16-byte aligned.
+ *   capacity      host uint64[n]; must be >= cmp_rle_max_size(image w, h,
+ *                 nplanes), which bounds every ROI's stream.
+ *   out_size_dev  device uint64[n]: the stream sizes.
+ *   status_dev    NULL or device int32[n]; a bounded wait that gives up
+ *                 stores CMP_ETIMEOUT there (never expected).
+ *   workspace     device, >= cmp_rle_workspace_size(imgs, n) bytes,
+ *                 zero-filled before its first use; calls leave it ready for
+ *                 the next call. Calls sharing a workspace must not overlap.
+ * n <= 64. Errors: CMP_EINVAL, CMP_ENOSPC, CMP_EUNSUPPORTED, CMP_EHIP.
+ */
+size_t     cmp_rle_workspace_size(const cmp_image* imgs, int32_t n);
+cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_format fmt,
+                            const int32_t* roi_dev, uint8_t* const* out,
+                            const uint64_t* capacity, uint64_t* out_size_dev,
+                            int32_t* status_dev, void* workspace, size_t ws_bytes,
+                            void* stream);
+
+/*
+ * Decompress n RLE1 streams in one launch.
+ *   in            host array of n device pointers (16-byte aligned).
+ *   in_bytes      host uint64[n]: readable bytes of each stream buffer.
+ *   out[i]        destination: color (uint32) and, for 8-plane streams,
+ *                 depth; pitch; out[i].roi.w/h bound the decoded ROI size.
+ *   roi_out_dev   NULL or device int32[n][4]: the ROI from each header.
+ *   status_dev    device int32[n], zero before the call; receives
+ *                 CMP_ECORRUPT (malformed stream) or CMP_ENOSPC (ROI larger
+ *                 than out[i].roi.w/h, or 8 planes without a depth buffer).
+ *                 Blocks of a bad stream may be left unwritten.
+ * n <= 64. Errors: CMP_EINVAL, CMP_EHIP.
+ */
+cmp_status cmp_rle_decompress(const uint8_t* const* in, const uint64_t* in_bytes, int32_t n,
+                              const cmp_image* out, int32_t* roi_out_dev, int32_t* status_dev,
+                              void* stream);
+
+/*
+ * Batched compositing: many independent jobs in one persistent launch whose
+ * workgroups pull (job, tile) work items from a device queue, largest first
+ * (the pull model of tile work packages, Section 4.2.4 Tiles and Section
+ * 6.2.1 Dynamic Work Packages).
+ *   kind 0: a cmp_composite_depth job (SEQ), kind 1: cmp_composite_over (SEQ).
+ * Each job's results are bit-identical to the plain call.
+ */
+typedef struct {
+  int32_t          kind;       /* 0 depth, 1 over                              */
+  cmp_format       fmt;        /* over: CMP_RGBA32F or CMP_RGBA16F             */
+  int32_t          n;
+  const cmp_image* in;         /* host array of n                              */
+  const int32_t*   order_b2f;  /* over: host, back to front                    */
+  cmp_rect         viewport;
+  void*            out_color;  /* depth: uint32; over: float RGBA              */
+  uint32_t*        out_depth;  /* depth: NULL or uint32                        */
+  int64_t          out_pitch;
+} cmp_job;
+
+typedef struct cmp_batch_plan cmp_batch_plan;
+
+/* Builds the work list on the host. tune_cache_path: NULL, or a text file
+ * written by cmp_autotune whose tile choices are used. */
+cmp_status cmp_batch_plan_create(const cmp_job* jobs, int32_t njobs, const char* tune_cache_path,
+                                 cmp_batch_plan** plan);
+size_t     cmp_batch_workspace_size(const cmp_batch_plan* plan);
+/* Copies the plan's tables into `workspace` (device) and prepares its queue
+ * counters. The plan must stay alive until the copy has completed. */
+cmp_status cmp_batch_upload(const cmp_batch_plan* plan, void* workspace, size_t ws_bytes,
+                            void* stream);
+/* One persistent launch over every work item; stream-capturable. */
+cmp_status cmp_batch_run(const cmp_batch_plan* plan, void* workspace, void* stream);
+/* The same jobs as one plain launch per job (the comparison baseline). */
+cmp_status cmp_batch_run_plain(const cmp_batch_plan* plan, void* stream);
+/* Work items and tiles of the plan (for reporting). */
+cmp_status cmp_batch_info(const cmp_batch_plan* plan, int64_t* items, int32_t* workgroups);
+void       cmp_batch_plan_destroy(cmp_batch_plan* plan);
+
+/*
+ * Autotuner: for every (kind, format, contributor-count bucket, size bucket)
+ * that occurs in `jobs`, times each candidate tile with plain launches of a
+ * representative job on `stream` (synchronising it) and writes the fastest
+ * tile per bucket to the text file `cache_path`. Results never depend on the
+ * tile. Writes only the jobs' outputs.
+ */
+cmp_status cmp_autotune(const cmp_job* jobs, int32_t njobs, const char* cache_path, int32_t reps,
+                        void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CMP_H */

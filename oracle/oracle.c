@@ -342,7 +342,8 @@ orc_rect orc_roi_detect_rgbaf(const double* rgba, int32_t w, int32_t h, int64_t 
 /* decoder tells the two apart by size == len_b.                            */
 /* Layout (all integers little-endian uint32):                              */
 /*   [0..32)  magic 0x31454C52, roi.x, roi.y, roi.w, roi.h, nplanes,        */
-/*            4096, nblocks = ceil(w h / 4096)                              */
+/*            4096, nblocks = ceil(w h / 4096); an empty ROI is stored as   */
+/*            (0, 0, 0, 0)                                                  */
 /*   boff[nblocks]          payload-relative offset of block b (16-aligned) */
 /*   size[nblocks][nplanes] encoded bytes of (block, plane)                 */
 /*   zero bytes up to the next multiple of 16: payload start P0             */
@@ -401,6 +402,7 @@ uint64_t orc_rle_compress(const uint32_t* color, const uint32_t* depth, int64_t 
 {
     const int32_t nplanes = depth ? 8 : 4;
     if (roi.w < 0 || roi.h < 0) return 0;
+    if (roi.w == 0 || roi.h == 0) { roi.x = 0; roi.y = 0; roi.w = 0; roi.h = 0; } /* canonical empty ROI */
     const int64_t npx = (int64_t)roi.w * roi.h;
     const uint64_t nb = rle_nblocks(npx);
     const uint64_t P0 = rle_payload_start(nb, nplanes);

@@ -1,0 +1,108 @@
+// Internal definitions shared by the HIP translation units of libcmp.
+// Target: gfx950 (CDNA4), wave64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "cmp.h"
+
+namespace cmp {
+
+constexpr uint32_t kClearDepth = 0xFFFFFFFFu;
+constexpr int kThreads = 256;   // every kernel runs 256-thread workgroups (4 waves)
+constexpr int kWave = 64;
+
+// ----------------------------------------------------------------- host
+void set_error(const char* fmt, ...);
+cmp_status hip_fail(hipError_t e, const char* what);
+
+#define CMP_CHECK_HIP(expr)                                  \
+  do {                                                       \
+    hipError_t e_ = (expr);                                  \
+    if (e_ != hipSuccess) return ::cmp::hip_fail(e_, #expr); \
+  } while (0)
+
+#define CMP_REQUIRE(cond, ...)                \
+  do {                                        \
+    if (!(cond)) {                            \
+      ::cmp::set_error(__VA_ARGS__);          \
+      return CMP_EINVAL;                      \
+    }                                         \
+  } while (0)
+
+inline bool rect_valid(cmp_rect r) { return r.w >= 0 && r.h >= 0; }
+inline bool rect_empty(cmp_rect r) { return r.w <= 0 || r.h <= 0; }
+
+// Launch geometry of a schedule: a list of regions of the viewport, each cut
+// into workgroup tiles (row-major inside the region).
+struct Region {
+  int32_t x, y, w, h;     // destination pixels
+  int32_t tile_begin;     // first workgroup of this region
+};
+constexpr int kMaxRegions = 64;
+
+// Builds the regions of `sched` over `vp`. Returns the number of regions (or
+// a negative cmp_status) and the total number of workgroup tiles.
+int plan_regions(cmp_schedule sched, cmp_rect vp, int tile_w, int tile_h, Region* out,
+                 int64_t* total_tiles);
+
+// --------------------------------------------------------------- device
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+
+// 16-byte load/store from an address that is only 4-byte aligned. gfx950
+// handles dword-aligned multi-dword global accesses.
+__device__ __forceinline__ u32x4 ld_u32x4(const uint32_t* p) {
+  u32x4 v;
+  __builtin_memcpy(&v, __builtin_assume_aligned(p, 4), 16);
+  return v;
+}
+__device__ __forceinline__ void st_u32x4(uint32_t* p, u32x4 v) {
+  __builtin_memcpy(__builtin_assume_aligned(p, 4), &v, 16);
+}
+
+// One RGBA pixel of a float layer as float4 (RGBA32F: 16-byte aligned load;
+// RGBA16F: 8-byte aligned load, exact widening).
+template <int FMT>
+__device__ __forceinline__ f32x4 ld_rgba(const void* base, int64_t px) {
+  if constexpr (FMT == CMP_RGBA32F) {
+    return reinterpret_cast<const f32x4*>(base)[px];
+  } else {
+    const f16x4 h = reinterpret_cast<const f16x4*>(base)[px];
+    return f32x4{(float)h.x, (float)h.y, (float)h.z, (float)h.w};
+  }
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m));
+  return v;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// The placement of contributor i: the host rectangle, or the device one
+// (clamped to the host rectangle's size, which bounds the buffer).
+__device__ __forceinline__ void placement(const int32_t* roi_dev, int idx, int32_t hx, int32_t hy,
+                                          int32_t hw, int32_t hh, int32_t& x, int32_t& y,
+                                          int32_t& w, int32_t& h) {
+  if (roi_dev) {
+    const int4 r = reinterpret_cast<const int4*>(roi_dev)[idx];
+    x = uniform(r.x);
+    y = uniform(r.y);
+    w = uniform(max(0, min(r.z, hw)));
+    h = uniform(max(0, min(r.w, hh)));
+  } else {
+    x = hx; y = hy; w = hw; h = hh;
+  }
+}
+
+}  // namespace cmp

@@ -1,0 +1,710 @@
+// cmp_rle_compress / cmp_rle_decompress: per-component run-length encoding of
+// RGBA8 (+ depth) pixels in the RLE1 format (Section 5.5.1, Enhanced RLE
+// Compression: one stream per pixel component; the image is decomposed into
+// sub-images compressed in parallel). Format: see cmp.h.
+//
+// Compression is a single pass over the input. A workgroup owns one block of
+// 4096 pixels of one image (16 consecutive pixels per lane) and encodes all
+// planes of it from registers:
+//   - run starts: byte != previous byte, or a multiple of 256 pixels; the
+//     previous lane's last byte comes from a lane shuffle (a wave boundary is
+//     always a 256-pixel boundary);
+//   - token slots: a workgroup-wide exclusive scan of the per-lane run counts
+//     (eight 16-bit counters packed in two 64-bit words);
+//   - run ends: the next start in the lane, else a suffix minimum of the first
+//     starts over the following lanes of the same 256-pixel segment;
+//   - the encoded block is staged in LDS, and its payload offset comes from a
+//     decoupled look-back over the blocks of the image (Merrill and Garland,
+//     "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016).
+//     Blocks are claimed with an atomic ticket, so every predecessor a block
+//     waits for is already running; the wait is bounded all the same.
+// The ticket, a completion counter and an epoch that tags the look-back
+// flags of one call live in the caller's workspace; the last workgroup
+// resets the counters and advances the epoch, so no clearing is needed
+// between calls.
+//
+// Decompression: a workgroup decodes one block: header and table checks,
+// payload to LDS, per plane a scan of the run lengths and, per lane, a binary
+// search for its first run; pixels are assembled in registers and written
+// with 16-byte stores.
+#include <string.h>
+
+#include "cmp_internal.hpp"
+
+namespace cmp {
+
+constexpr uint32_t kRleMagic = 0x31454C52u;
+constexpr int kBlock = 4096;
+constexpr int kSeg = 256;
+constexpr int kPxPerLane = 16;
+constexpr int kRleMax = 64;
+constexpr int kStage = 8 * kBlock + 16;
+
+__host__ __device__ inline int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
+__host__ __device__ inline uint64_t align16(uint64_t v) { return (v + 15u) & ~(uint64_t)15u; }
+__host__ __device__ inline uint64_t rle_nblocks(int64_t npx) {
+  return (uint64_t)((npx + kBlock - 1) / kBlock);
+}
+__host__ __device__ inline uint64_t rle_p0(uint64_t nb, int np) {
+  return align16(32 + 4 * nb * (1 + (uint64_t)np));
+}
+
+// ------------------------------------------------------------- helpers
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
+  const int lane = threadIdx.x % kWave;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint64_t o = __shfl_up(v, d);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Exclusive workgroup scan of two packed words (4 x 16-bit counters each);
+// also returns the workgroup totals. `sh` holds 8 words; ends with a barrier.
+__device__ __forceinline__ void block_scan2(uint64_t a, uint64_t b, uint64_t& ea, uint64_t& eb,
+                                            uint64_t& ta, uint64_t& tb, uint64_t* sh) {
+  const uint64_t ia = wave_incl_scan(a), ib = wave_incl_scan(b);
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (lane == kWave - 1) {
+    sh[wave] = ia;
+    sh[4 + wave] = ib;
+  }
+  __syncthreads();
+  uint64_t pa = 0, pb = 0;
+  ta = 0;
+  tb = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / kWave; ++w) {
+    if (w < wave) {
+      pa += sh[w];
+      pb += sh[4 + w];
+    }
+    ta += sh[w];
+    tb += sh[4 + w];
+  }
+  ea = pa + ia - a;
+  eb = pb + ib - b;
+  __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t field16(uint64_t lo, uint64_t hi, int k) {
+  const uint64_t w = k < 4 ? lo : hi;
+  return (uint32_t)((w >> (16 * (k & 3))) & 0xFFFFu);
+}
+
+__device__ __forceinline__ uint32_t byte_of(uint32_t w, int k) { return (w >> (8 * (k & 3))) & 0xFFu; }
+
+// Clamp a device ROI to a W x H image.
+__device__ __forceinline__ void clamp_roi(const int32_t* roi_dev, int s, int W, int H, int& x,
+                                          int& y, int& w, int& h) {
+  if (!roi_dev) {
+    x = 0; y = 0; w = W; h = H;
+    return;
+  }
+  const int4 r = reinterpret_cast<const int4*>(roi_dev)[s];
+  x = min(max(r.x, 0), W);
+  y = min(max(r.y, 0), H);
+  w = min(max(r.z, 0), W - x);
+  h = min(max(r.w, 0), H - y);
+  if (w == 0 || h == 0) { x = 0; y = 0; w = 0; h = 0; }
+  x = uniform(x); y = uniform(y); w = uniform(w); h = uniform(h);
+}
+
+// ------------------------------------------------------------ compress
+struct RleCImg {
+  const uint32_t* color;
+  const uint32_t* depth;   // nullptr: 4 planes
+  int64_t pitch;
+  int32_t W, H;            // image size
+  uint8_t* out;
+  int32_t flag_base;       // first look-back flag of this image
+  int32_t pad;
+};
+
+struct RleCArgs {
+  RleCImg im[kRleMax];
+  const int32_t* roi_dev;
+  uint64_t* out_size;
+  int32_t* status;
+  uint32_t* ctl;           // workspace: [0] ticket, [1] done, [2] epoch
+  uint64_t* flags;         // workspace: one flag per (image, block)
+  int32_t n;
+};
+static_assert(sizeof(RleCArgs) <= 4096, "kernel arguments must fit in 4 KiB");
+
+// look-back flag: epoch (30 bits) | status (2 bits) | value (32 bits)
+constexpr uint64_t kAgg = 1, kIncl = 2;
+__device__ __forceinline__ uint64_t mkflag(uint32_t epoch, uint64_t st, uint32_t v) {
+  return ((uint64_t)(epoch & 0x3FFFFFFFu) << 34) | (st << 32) | v;
+}
+
+__global__ __launch_bounds__(kThreads) void rle_compress_kernel(const RleCArgs a) {
+  __shared__ __attribute__((aligned(16))) uint8_t stage[kStage];
+  __shared__ uint64_t sh[8];
+  __shared__ uint32_t s_ticket, s_epoch, s_excl;
+  const int tid = threadIdx.x;
+  const int lane = tid % kWave;
+  if (tid == 0) {
+    s_ticket = atomicAdd(&a.ctl[0], 1u);
+    s_epoch = __hip_atomic_load(&a.ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  const uint32_t ticket = s_ticket, epoch = s_epoch;
+
+  // ticket -> (image, block); an image with an empty ROI still takes one
+  // ticket, whose workgroup writes its header-only stream
+  int s = -1, b = 0, rx = 0, ry = 0, rw = 0, rh = 0;
+  {
+    uint32_t t = ticket;
+    for (int i = 0; i < a.n; ++i) {
+      int x, y, w, h;
+      clamp_roi(a.roi_dev, i, a.im[i].W, a.im[i].H, x, y, w, h);
+      const uint32_t nb = (uint32_t)rle_nblocks((int64_t)w * h);
+      const uint32_t slots = nb ? nb : 1;
+      if (t < slots) {
+        s = i; b = (int)t; rx = x; ry = y; rw = w; rh = h;
+        break;
+      }
+      t -= slots;
+    }
+  }
+  if (s >= 0) {
+    const RleCImg I = a.im[s];
+    const int np = I.depth ? 8 : 4;
+    const int64_t npx = (int64_t)rw * rh;
+    const uint64_t nb = rle_nblocks(npx);
+    const uint64_t P0 = rle_p0(nb, np);
+    uint8_t* out = I.out;
+    if (nb == 0) {
+      if (tid < 8) {
+        const uint32_t hdr[8] = {kRleMagic, (uint32_t)rx, (uint32_t)ry, 0u, 0u, (uint32_t)np,
+                                 (uint32_t)kBlock, 0u};
+        reinterpret_cast<uint32_t*>(out)[tid] = hdr[tid];
+      }
+      if (tid == 0) a.out_size[s] = 32;
+    } else {
+      const int len = (int)imin64(kBlock, npx - (int64_t)b * kBlock);
+      // ---- load this lane's 16 pixels
+      uint32_t col[kPxPerLane], dep[kPxPerLane];
+      const int q0 = tid * kPxPerLane;   // block-relative first pixel
+      {
+        const int64_t q = (int64_t)b * kBlock + q0;
+        int yy = (int)(q / rw), xx = (int)(q - (int64_t)yy * rw);
+        const bool fast = (q0 + kPxPerLane <= len) && (xx + kPxPerLane <= rw);
+        if (fast) {
+          const int64_t off = (int64_t)(ry + yy) * I.pitch + rx + xx;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const u32x4 c4 = ld_u32x4(I.color + off + 4 * v);
+            col[4 * v + 0] = c4.x; col[4 * v + 1] = c4.y; col[4 * v + 2] = c4.z; col[4 * v + 3] = c4.w;
+            if (np == 8) {
+              const u32x4 d4 = ld_u32x4(I.depth + off + 4 * v);
+              dep[4 * v + 0] = d4.x; dep[4 * v + 1] = d4.y; dep[4 * v + 2] = d4.z; dep[4 * v + 3] = d4.w;
+            } else {
+              dep[4 * v + 0] = dep[4 * v + 1] = dep[4 * v + 2] = dep[4 * v + 3] = 0;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < kPxPerLane; ++j) {
+            col[j] = 0;
+            dep[j] = 0;
+            if (q0 + j < len) {
+              const int64_t off = (int64_t)(ry + yy) * I.pitch + rx + xx;
+              col[j] = I.color[off];
+              if (np == 8) dep[j] = I.depth[off];
+              if (++xx == rw) { xx = 0; ++yy; }
+            }
+          }
+        }
+      }
+      const uint32_t pcol = __shfl_up(col[kPxPerLane - 1], 1);
+      const uint32_t pdep = __shfl_up(dep[kPxPerLane - 1], 1);
+      const bool seg_start = (tid % (kSeg / kPxPerLane)) == 0;
+      const int nvalid = min(kPxPerLane, max(0, len - q0));
+      const uint32_t vmask = (1u << nvalid) - 1u;
+
+      // ---- run starts and counts per plane
+      uint32_t masks[8];
+      uint64_t cnt_lo = 0, cnt_hi = 0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        masks[k] = 0;
+        if (k >= np) continue;
+        const uint32_t* w = k < 4 ? col : dep;
+        uint32_t m = 0;
+        uint32_t prev = byte_of(k < 4 ? pcol : pdep, k);
+#pragma unroll
+        for (int j = 0; j < kPxPerLane; ++j) {
+          const uint32_t c = byte_of(w[j], k);
+          const bool st = (j == 0) ? (seg_start || c != prev) : (c != prev);
+          m |= (uint32_t)st << j;
+          prev = c;
+        }
+        m &= vmask;
+        masks[k] = m;
+        const uint64_t c = (uint64_t)__builtin_popcount(m);
+        if (k < 4) cnt_lo |= c << (16 * k);
+        else cnt_hi |= c << (16 * (k - 4));
+      }
+      uint64_t ex_lo, ex_hi, tot_lo, tot_hi;
+      block_scan2(cnt_lo, cnt_hi, ex_lo, ex_hi, tot_lo, tot_hi, sh);
+
+      // ---- plane sizes and offsets (uniform)
+      uint32_t size[8], poff[8];
+      uint32_t total = 0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        size[k] = 0;
+        poff[k] = total;
+        if (k >= np) continue;
+        const uint32_t ntok = field16(tot_lo, tot_hi, k);
+        size[k] = (2 * ntok < (uint32_t)len) ? 2 * ntok : (uint32_t)len;
+        total += size[k];
+      }
+      const uint32_t padded = (uint32_t)align16(total);
+
+      // ---- stage the encoded block in LDS
+      const int seg_end = min(len, ((q0 / kSeg) + 1) * kSeg);
+      const int lig = tid % (kSeg / kPxPerLane);   // lane within its 256-pixel segment
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (k >= np) continue;
+        const uint32_t* w = k < 4 ? col : dep;
+        const uint32_t m = masks[k];
+        const uint32_t off = poff[k];
+        if (size[k] != (uint32_t)len) {
+          // first start of this lane, then the suffix minimum over later lanes
+          int fs = m ? q0 + __builtin_ctz(m) : seg_end;
+#pragma unroll
+          for (int d = 1; d < kSeg / kPxPerLane; d <<= 1) {
+            const int o = __shfl_down(fs, d, kSeg / kPxPerLane);
+            if (lig + d < kSeg / kPxPerLane) fs = min(fs, o);
+          }
+          const int nxt = __shfl_down(fs, 1, kSeg / kPxPerLane);
+          const int next_after = (lig == kSeg / kPxPerLane - 1) ? seg_end : nxt;
+          const uint32_t tok0 = field16(ex_lo, ex_hi, k);
+#pragma unroll
+          for (int j = 0; j < kPxPerLane; ++j) {
+            if ((m >> j) & 1u) {
+              const uint32_t rest = m >> (j + 1);
+              const int end = rest ? q0 + j + 1 + __builtin_ctz(rest) : next_after;
+              const uint32_t idx = tok0 + __builtin_popcount(m & ((1u << j) - 1u));
+              stage[off + 2 * idx] = (uint8_t)(end - (q0 + j) - 1);
+              stage[off + 2 * idx + 1] = (uint8_t)byte_of(w[j], k);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < kPxPerLane; ++j)
+            if (q0 + j < len) stage[off + q0 + j] = (uint8_t)byte_of(w[j], k);
+        }
+      }
+      if (tid < (int)(padded - total)) stage[total + tid] = 0;
+
+      // ---- decoupled look-back for the payload offset
+      if (tid == 0) {
+        uint64_t* flags = a.flags + I.flag_base;
+        uint32_t excl = 0;
+        if (b == 0) {
+          __hip_atomic_store(&flags[0], mkflag(epoch, kIncl, padded), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          __hip_atomic_store(&flags[b], mkflag(epoch, kAgg, padded), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+          int p = b - 1;
+          uint32_t spins = 0;
+          while (true) {
+            const uint64_t f =
+                __hip_atomic_load(&flags[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t fe = (uint32_t)(f >> 34);
+            const uint64_t st = (f >> 32) & 3u;
+            if (fe != (epoch & 0x3FFFFFFFu) || st == 0) {
+              if (++spins > (1u << 22)) {
+                if (a.status) a.status[s] = CMP_ETIMEOUT;
+                break;
+              }
+              __builtin_amdgcn_s_sleep(1);
+              continue;
+            }
+            excl += (uint32_t)f;
+            if (st == kIncl || p == 0) break;
+            --p;
+          }
+          __hip_atomic_store(&flags[b], mkflag(epoch, kIncl, excl + padded), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_excl = excl;
+      }
+      __syncthreads();
+      const uint32_t excl = s_excl;
+
+      // ---- tables, header, payload
+      uint32_t* tbl = reinterpret_cast<uint32_t*>(out + 32);
+      if (tid < np) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (k == tid) v = size[k];
+        tbl[nb + (uint64_t)b * np + tid] = v;
+      }
+      if (tid == 0) tbl[b] = excl;
+      if (b == 0) {
+        if (tid < 8) {
+          const uint32_t hdr[8] = {kRleMagic, (uint32_t)rx, (uint32_t)ry, (uint32_t)rw,
+                                   (uint32_t)rh, (uint32_t)np, (uint32_t)kBlock, (uint32_t)nb};
+          reinterpret_cast<uint32_t*>(out)[tid] = hdr[tid];
+        }
+        const uint64_t tend = 32 + 4 * nb * (1 + (uint64_t)np);
+        if ((uint64_t)tid < P0 - tend) out[tend + tid] = 0;
+      }
+      if ((uint64_t)b == nb - 1 && tid == 0) a.out_size[s] = P0 + excl + padded;
+      u32x4* dst = reinterpret_cast<u32x4*>(out + P0 + excl);
+      const u32x4* src = reinterpret_cast<const u32x4*>(stage);
+      for (uint32_t i = tid; i < padded / 16; i += kThreads) dst[i] = src[i];
+    }
+  }
+  // ---- completion: the last workgroup resets the counters for the next call
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    const uint32_t done = atomicAdd(&a.ctl[1], 1u);
+    if (done == gridDim.x - 1) {
+      __hip_atomic_store(&a.ctl[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&a.ctl[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&a.ctl[2], (epoch + 1u) & 0x3FFFFFFFu, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// ---------------------------------------------------------- decompress
+struct RleDImg {
+  const uint8_t* in;
+  uint64_t in_bytes;
+  uint32_t* color;
+  uint32_t* depth;
+  int64_t pitch;
+  int32_t cap_w, cap_h;
+  int32_t wg_begin, nwg;
+};
+
+struct RleDArgs {
+  RleDImg im[kRleMax];
+  int32_t* roi_out;
+  int32_t* status;
+  int32_t n;
+};
+static_assert(sizeof(RleDArgs) <= 4096, "kernel arguments must fit in 4 KiB");
+
+__global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs a) {
+  __shared__ __attribute__((aligned(16))) uint8_t stage[kStage];
+  __shared__ uint16_t ends[kBlock / 2];
+  __shared__ uint64_t sh[8];
+  __shared__ uint32_t s_hdr[8];
+  __shared__ uint32_t s_size[8];
+  __shared__ uint32_t s_boff;
+  __shared__ int32_t s_err;
+  const int tid = threadIdx.x;
+  const int blk = blockIdx.x;
+  int s = 0;
+  while (s + 1 < a.n && a.im[s + 1].wg_begin <= blk) ++s;
+  const RleDImg I = a.im[s];
+  const int b = blk - I.wg_begin;
+
+  // ---- header and this block's table entries
+  if (tid == 0) {
+    int err = 0;
+    uint32_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (I.in_bytes < 32) {
+      err = CMP_ECORRUPT;
+    } else {
+      const u32x4 h0 = reinterpret_cast<const u32x4*>(I.in)[0];
+      const u32x4 h1 = reinterpret_cast<const u32x4*>(I.in)[1];
+      h[0] = h0.x; h[1] = h0.y; h[2] = h0.z; h[3] = h0.w;
+      h[4] = h1.x; h[5] = h1.y; h[6] = h1.z; h[7] = h1.w;
+      const int32_t w = (int32_t)h[3], hh = (int32_t)h[4];
+      const uint32_t np = h[5];
+      if (h[0] != kRleMagic || w < 0 || hh < 0 || (np != 4 && np != 8) || h[6] != (uint32_t)kBlock)
+        err = CMP_ECORRUPT;
+      else if ((uint64_t)h[7] != rle_nblocks((int64_t)w * hh))
+        err = CMP_ECORRUPT;
+      else if (I.in_bytes < rle_p0(h[7], (int)np))
+        err = CMP_ECORRUPT;
+      else if (w > I.cap_w || hh > I.cap_h || (np == 8 && !I.depth))
+        err = CMP_ENOSPC;
+    }
+    uint32_t boff = 0;
+    if (!err && (uint32_t)b < h[7]) {
+      const uint64_t nb = h[7];
+      const int np = (int)h[5];
+      const int64_t npx = (int64_t)(int32_t)h[3] * (int32_t)h[4];
+      const uint32_t len = (uint32_t)imin64(kBlock, npx - (int64_t)b * kBlock);
+      const uint32_t* tbl = reinterpret_cast<const uint32_t*>(I.in + 32);
+      boff = tbl[b];
+      uint64_t tot = 0;
+      for (int k = 0; k < np; ++k) {
+        const uint32_t sz = tbl[nb + (uint64_t)b * np + k];
+        s_size[k] = sz;
+        if (sz > len || (sz < len && (sz == 0 || (sz & 1u)))) err = CMP_ECORRUPT;
+        tot += sz;
+      }
+      const uint64_t P0 = rle_p0(nb, np);
+      if ((boff & 15u) || (b == 0 && boff != 0)) err = CMP_ECORRUPT;
+      if ((uint64_t)b + 1 < nb && (uint64_t)tbl[b + 1] != boff + align16(tot)) err = CMP_ECORRUPT;
+      if (P0 + boff + align16(tot) > I.in_bytes) err = CMP_ECORRUPT;
+    }
+    if (err && (b == 0 || err == CMP_ECORRUPT)) a.status[s] = err;
+    for (int k = 0; k < 8; ++k) s_hdr[k] = h[k];
+    s_boff = boff;
+    s_err = err;
+  }
+  __syncthreads();
+  if (s_err) return;
+  const int32_t rw = (int32_t)s_hdr[3], rh = (int32_t)s_hdr[4];
+  const int np = (int)s_hdr[5];
+  const uint64_t nb = s_hdr[7];
+  if (b == 0 && a.roi_out && tid < 4)
+    a.roi_out[4 * s + tid] = (int32_t)(tid == 0 ? s_hdr[1] : tid == 1 ? s_hdr[2] : s_hdr[3 + tid - 2]);
+  if ((uint64_t)b >= nb) return;
+  const int64_t npx = (int64_t)rw * rh;
+  const int len = (int)imin64(kBlock, npx - (int64_t)b * kBlock);
+  uint32_t size[8], poff[8], total = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    size[k] = k < np ? s_size[k] : 0;
+    poff[k] = total;
+    total += size[k];
+  }
+  const uint32_t padded = (uint32_t)align16(total);
+  {
+    const u32x4* src = reinterpret_cast<const u32x4*>(I.in + rle_p0(nb, np) + s_boff);
+    u32x4* dst = reinterpret_cast<u32x4*>(stage);
+    for (uint32_t i = tid; i < padded / 16; i += kThreads) dst[i] = src[i];
+  }
+  __syncthreads();
+
+  const int q0 = tid * kPxPerLane;
+  uint32_t col[kPxPerLane], dep[kPxPerLane];
+#pragma unroll
+  for (int j = 0; j < kPxPerLane; ++j) { col[j] = 0; dep[j] = 0; }
+  bool bad = false;
+  for (int k = 0; k < np; ++k) {
+    const uint32_t off = poff[k];
+    const int sh8 = 8 * (k & 3);
+    if (size[k] == (uint32_t)len) {
+#pragma unroll
+      for (int j = 0; j < kPxPerLane; ++j) {
+        if (q0 + j < len) {
+          const uint32_t v = stage[off + q0 + j];
+          if (k < 4) col[j] |= v << sh8; else dep[j] |= v << sh8;
+        }
+      }
+      continue;
+    }
+    // run lengths -> inclusive ends (8 tokens per lane)
+    const int ntok = (int)(size[k] / 2);
+    uint32_t lens[8];
+    uint32_t mysum = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int ti = tid * 8 + t;
+      lens[t] = ti < ntok ? (uint32_t)stage[off + 2 * ti] + 1u : 0u;
+      mysum += lens[t];
+    }
+    uint64_t ex, ex2, tot, tot2;
+    block_scan2(mysum, 0, ex, ex2, tot, tot2, sh);
+    uint32_t run = (uint32_t)ex;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int ti = tid * 8 + t;
+      run += lens[t];
+      if (ti < ntok) ends[ti] = (uint16_t)min(run, 65535u);
+    }
+    if ((uint32_t)tot != (uint32_t)len) bad = true;   // uniform
+    __syncthreads();
+    if (!bad && q0 < len) {
+      // first run that ends after q0
+      int lo = 0, hi = ntok - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)ends[mid] > q0) hi = mid; else lo = mid + 1;
+      }
+      int tok = lo;
+      int e = ends[tok];
+      uint32_t v = stage[off + 2 * tok + 1];
+#pragma unroll
+      for (int j = 0; j < kPxPerLane; ++j) {
+        const int pos = q0 + j;
+        if (pos < len) {
+          while (pos >= e && tok + 1 < ntok) {
+            ++tok;
+            e = ends[tok];
+            v = stage[off + 2 * tok + 1];
+          }
+          if (k < 4) col[j] |= v << sh8; else dep[j] |= v << sh8;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) a.status[s] = CMP_ECORRUPT;
+    return;
+  }
+  // ---- write the pixels (row-major over the ROI)
+  if (q0 < len) {
+    const int64_t q = (int64_t)b * kBlock + q0;
+    int yy = (int)(q / rw), xx = (int)(q - (int64_t)yy * rw);
+    const bool fast = (q0 + kPxPerLane <= len) && (xx + kPxPerLane <= rw);
+    if (fast) {
+      const int64_t o = (int64_t)yy * I.pitch + xx;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        st_u32x4(I.color + o + 4 * v,
+                 u32x4{col[4 * v], col[4 * v + 1], col[4 * v + 2], col[4 * v + 3]});
+        if (np == 8)
+          st_u32x4(I.depth + o + 4 * v,
+                   u32x4{dep[4 * v], dep[4 * v + 1], dep[4 * v + 2], dep[4 * v + 3]});
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kPxPerLane; ++j) {
+        if (q0 + j < len) {
+          const int64_t o = (int64_t)yy * I.pitch + xx;
+          I.color[o] = col[j];
+          if (np == 8) I.depth[o] = dep[j];
+          if (++xx == rw) { xx = 0; ++yy; }
+        }
+      }
+    }
+  }
+}
+
+// Look-back flags: one per block of each image's largest possible ROI.
+static int64_t rle_flag_count(const cmp_image* imgs, int32_t n) {
+  int64_t f = 0;
+  for (int i = 0; i < n; ++i) {
+    const int64_t npx = (int64_t)(imgs[i].roi.w > 0 ? imgs[i].roi.w : 0) *
+                        (imgs[i].roi.h > 0 ? imgs[i].roi.h : 0);
+    const int64_t nb = (int64_t)rle_nblocks(npx);
+    f += nb ? nb : 1;
+  }
+  return f;
+}
+
+}  // namespace cmp
+
+using namespace cmp;
+
+extern "C" size_t cmp_rle_max_size(int32_t w, int32_t h, int32_t nplanes) {
+  if (w < 0 || h < 0 || nplanes <= 0) return 0;
+  const int64_t npx = (int64_t)w * h;
+  const uint64_t nb = rle_nblocks(npx);
+  uint64_t total = rle_p0(nb, nplanes);
+  if (nb) total += (nb - 1) * align16((uint64_t)kBlock * nplanes) +
+                   align16((uint64_t)(npx - (int64_t)(nb - 1) * kBlock) * nplanes);
+  return (size_t)total;
+}
+
+extern "C" size_t cmp_rle_workspace_size(const cmp_image* imgs, int32_t n) {
+  if (n < 0 || (n > 0 && !imgs)) return 0;
+  return (size_t)(64 + 8 * rle_flag_count(imgs, n));
+}
+
+extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_format fmt,
+                                       const int32_t* roi_dev, uint8_t* const* out,
+                                       const uint64_t* capacity, uint64_t* out_size_dev,
+                                       int32_t* status_dev, void* workspace, size_t ws_bytes,
+                                       void* stream) {
+  CMP_REQUIRE(n >= 0 && n <= kRleMax, "n = %d must be 0..%d", n, kRleMax);
+  if (n == 0) return CMP_OK;
+  if (fmt != CMP_RGBA8) {
+    set_error("RLE compression handles RGBA8 (+ depth) pixels");
+    return CMP_EUNSUPPORTED;
+  }
+  CMP_REQUIRE(imgs && out && capacity && out_size_dev && workspace, "NULL argument");
+  CMP_REQUIRE(((uintptr_t)roi_dev & 15) == 0 && ((uintptr_t)workspace & 15) == 0 &&
+                  ((uintptr_t)out_size_dev & 7) == 0,
+              "roi_dev/workspace must be 16-byte and out_size_dev 8-byte aligned");
+  RleCArgs a;
+  memset(&a, 0, sizeof a);
+  int64_t grid = 0, flags = 0;
+  for (int i = 0; i < n; ++i) {
+    const cmp_image& I = imgs[i];
+    CMP_REQUIRE(rect_valid(I.roi), "imgs[%d] has a negative size", i);
+    const int W = rect_empty(I.roi) ? 0 : I.roi.w, H = rect_empty(I.roi) ? 0 : I.roi.h;
+    if (W > 0) {
+      CMP_REQUIRE(I.color, "imgs[%d].color is NULL", i);
+      CMP_REQUIRE(I.pitch >= W, "imgs[%d].pitch < width", i);
+      CMP_REQUIRE(((uintptr_t)I.color & 3) == 0 && ((uintptr_t)I.depth & 3) == 0,
+                  "imgs[%d]: buffers must be 4-byte aligned", i);
+    }
+    const int np = I.depth ? 8 : 4;
+    CMP_REQUIRE(out[i] && ((uintptr_t)out[i] & 15) == 0, "out[%d] must be 16-byte aligned", i);
+    const size_t need = cmp_rle_max_size(W, H, np);
+    CMP_REQUIRE(need < (1ull << 32), "image %d too large for 32-bit stream offsets", i);
+    if (capacity[i] < need) {
+      set_error("capacity[%d] = %llu < %zu", i, (unsigned long long)capacity[i], need);
+      return CMP_ENOSPC;
+    }
+    const int64_t nb = (int64_t)rle_nblocks((int64_t)W * H);
+    a.im[i] = RleCImg{(const uint32_t*)I.color, I.depth, I.pitch, W, H, out[i], (int32_t)flags, 0};
+    flags += nb ? nb : 1;
+    grid += nb ? nb : 1;
+  }
+  CMP_REQUIRE(grid < (1ll << 24), "too many blocks");
+  const size_t need = (size_t)(64 + 8 * flags);
+  if (ws_bytes < need) {
+    set_error("workspace of %zu bytes is smaller than %zu", ws_bytes, need);
+    return CMP_ENOSPC;
+  }
+  a.roi_dev = roi_dev;
+  a.out_size = out_size_dev;
+  a.status = status_dev;
+  a.ctl = (uint32_t*)workspace;
+  a.flags = (uint64_t*)((char*)workspace + 64);
+  a.n = n;
+  hipLaunchKernelGGL(rle_compress_kernel, dim3((unsigned)grid), dim3(kThreads), 0,
+                     (hipStream_t)stream, a);
+  CMP_CHECK_HIP(hipGetLastError());
+  return CMP_OK;
+}
+
+extern "C" cmp_status cmp_rle_decompress(const uint8_t* const* in, const uint64_t* in_bytes,
+                                         int32_t n, const cmp_image* out, int32_t* roi_out_dev,
+                                         int32_t* status_dev, void* stream) {
+  CMP_REQUIRE(n >= 0 && n <= kRleMax, "n = %d must be 0..%d", n, kRleMax);
+  if (n == 0) return CMP_OK;
+  CMP_REQUIRE(in && in_bytes && out && status_dev, "NULL argument");
+  CMP_REQUIRE(((uintptr_t)roi_out_dev & 15) == 0 && ((uintptr_t)status_dev & 3) == 0,
+              "roi_out_dev must be 16-byte aligned");
+  RleDArgs a;
+  memset(&a, 0, sizeof a);
+  int64_t grid = 0;
+  for (int i = 0; i < n; ++i) {
+    const cmp_image& O = out[i];
+    CMP_REQUIRE(in[i] && ((uintptr_t)in[i] & 15) == 0, "in[%d] must be 16-byte aligned", i);
+    CMP_REQUIRE(rect_valid(O.roi), "out[%d] has a negative size", i);
+    const int W = rect_empty(O.roi) ? 0 : O.roi.w, H = rect_empty(O.roi) ? 0 : O.roi.h;
+    if (W > 0) {
+      CMP_REQUIRE(O.color && O.pitch >= W, "out[%d]: NULL colour or pitch < width", i);
+      CMP_REQUIRE(((uintptr_t)O.color & 3) == 0 && ((uintptr_t)O.depth & 3) == 0,
+                  "out[%d]: buffers must be 4-byte aligned", i);
+    }
+    const int64_t nb = (int64_t)rle_nblocks((int64_t)W * H);
+    const int nwg = (int)(nb ? nb : 1);
+    a.im[i] = RleDImg{in[i], in_bytes[i], (uint32_t*)O.color, (uint32_t*)O.depth, O.pitch, W, H,
+                      (int32_t)grid, nwg};
+    grid += nwg;
+  }
+  CMP_REQUIRE(grid < (1ll << 24), "too many blocks");
+  a.roi_out = roi_out_dev;
+  a.status = status_dev;
+  a.n = n;
+  hipLaunchKernelGGL(rle_decompress_kernel, dim3((unsigned)grid), dim3(kThreads), 0,
+                     (hipStream_t)stream, a);
+  CMP_CHECK_HIP(hipGetLastError());
+  return CMP_OK;
+}

@@ -1,0 +1,271 @@
+// cmp_roi_detect: automatic region-of-interest detection, the 2D bounding box
+// of the pixels that hold data (Section 5.3, Region of Interest).
+//
+// One pass over every image, several images per launch. A workgroup scans a
+// band of rows with 16-byte loads (4 depth or RGBA8 pixels, 2 RGBA16F pixels
+// or 1 RGBA32F pixel per load), keeps per-lane min/max of the data pixels'
+// columns and rows, reduces them across the wave and the workgroup, and
+// stores one partial box. The last workgroup of an image (counted with an
+// atomic ticket) folds the partial boxes into the final rectangle and resets
+// the ticket, so the workspace is ready for the next call.
+#include <string.h>
+
+#include "cmp_internal.hpp"
+
+namespace cmp {
+
+constexpr int kRoiMax = 64;
+
+struct RoiImg {
+  const void* color;
+  const uint32_t* depth;
+  int64_t pitch;
+  int32_t w, h;
+  int32_t wg_begin;   // first workgroup of this image
+  int32_t nwg;        // workgroups of this image
+  int32_t rows;       // rows per workgroup
+  int32_t part_base;  // first partial slot
+};
+
+struct RoiArgs {
+  RoiImg im[kRoiMax];
+  int32_t* roi_out;
+  int32_t* ticket;    // workspace: int32[n]
+  int4* part;         // workspace: int4[total workgroups]
+  int32_t n;
+  int32_t mode;       // 0 depth, 1 RGBA8 colour, 2 RGBA32F, 3 RGBA16F
+};
+static_assert(sizeof(RoiArgs) <= 4096, "kernel arguments must fit in 4 KiB");
+
+// Bit k of the result is set when pixel k of the 16-byte unit holds data.
+template <int MODE>
+__device__ __forceinline__ uint32_t unit_mask(u32x4 v) {
+  if constexpr (MODE == 0) {
+    return (v.x != kClearDepth) | ((v.y != kClearDepth) << 1) | ((v.z != kClearDepth) << 2) |
+           ((v.w != kClearDepth) << 3);
+  } else if constexpr (MODE == 1) {
+    return (v.x != 0u) | ((v.y != 0u) << 1) | ((v.z != 0u) << 2) | ((v.w != 0u) << 3);
+  } else if constexpr (MODE == 2) {
+    // any channel != 0.0: -0.0 is empty, NaN holds data
+    return ((v.x | v.y | v.z | v.w) & 0x7FFFFFFFu) != 0u;
+  } else {
+    const uint32_t a = (v.x & 0x7FFF7FFFu) | (v.y & 0x7FFF7FFFu);
+    const uint32_t b = (v.z & 0x7FFF7FFFu) | (v.w & 0x7FFF7FFFu);
+    return (a != 0u) | ((b != 0u) << 1);
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ uint32_t px_mask(const uint8_t* row, int x) {
+  if constexpr (MODE == 0 || MODE == 1) {
+    const uint32_t v = reinterpret_cast<const uint32_t*>(row)[x];
+    return MODE == 0 ? v != kClearDepth : v != 0u;
+  } else if constexpr (MODE == 2) {
+    const u32x4 v = reinterpret_cast<const u32x4*>(row)[x];
+    return ((v.x | v.y | v.z | v.w) & 0x7FFFFFFFu) != 0u;
+  } else {
+    const uint2 v = reinterpret_cast<const uint2*>(row)[x];
+    return ((v.x | v.y) & 0x7FFF7FFFu) != 0u;
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void roi_kernel(const RoiArgs a) {
+  constexpr int bpp = MODE == 2 ? 16 : MODE == 3 ? 8 : 4;
+  constexpr int ppu = 16 / bpp;  // pixels per 16-byte unit
+  const int blk = blockIdx.x;
+  int s = 0;
+  while (s + 1 < a.n && a.im[s + 1].wg_begin <= blk) ++s;
+  const RoiImg I = a.im[s];
+  const int local = blk - I.wg_begin;
+  const int y0 = local * I.rows;
+  const int y1 = min(I.h, y0 + I.rows);
+  const uint8_t* base =
+      reinterpret_cast<const uint8_t*>(MODE == 0 ? (const void*)I.depth : I.color);
+  const int64_t row_bytes = I.pitch * bpp;
+  // 16-byte units per row, and whether the row start is 16-byte aligned
+  const bool aligned = ((reinterpret_cast<uintptr_t>(base) | (uintptr_t)row_bytes) & 15) == 0;
+  const int full_units = aligned ? I.w / ppu : 0;
+  const int tail = I.w - full_units * ppu;   // pixels handled one by one
+
+  int minx = 0x7FFFFFFF, miny = 0x7FFFFFFF, maxx = -1, maxy = -1;
+  const int per_row = full_units + tail;
+  const int work = per_row * (y1 - y0);
+  for (int t = threadIdx.x; t < work; t += kThreads) {
+    const int ry = t / per_row;
+    const int u = t - ry * per_row;
+    const int y = y0 + ry;
+    const uint8_t* row = base + (int64_t)y * row_bytes;
+    uint32_t m;
+    int x;
+    if (u < full_units) {
+      m = unit_mask<MODE>(reinterpret_cast<const u32x4*>(row)[u]);
+      x = u * ppu;
+    } else {
+      x = full_units * ppu + (u - full_units);
+      m = px_mask<MODE>(row, x);
+    }
+    if (m) {
+      minx = min(minx, x + (int)__builtin_ctz(m));
+      maxx = max(maxx, x + 31 - (int)__builtin_clz(m));
+      miny = min(miny, y);
+      maxy = max(maxy, y);
+    }
+  }
+  __shared__ int4 red[kThreads / kWave];
+  minx = wave_min(minx);
+  miny = wave_min(miny);
+  maxx = wave_max(maxx);
+  maxy = wave_max(maxy);
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (lane == 0) red[wave] = int4{minx, miny, maxx, maxy};
+  __syncthreads();
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    int4 b = red[0];
+#pragma unroll
+    for (int w = 1; w < kThreads / kWave; ++w) {
+      b.x = min(b.x, red[w].x);
+      b.y = min(b.y, red[w].y);
+      b.z = max(b.z, red[w].z);
+      b.w = max(b.w, red[w].w);
+    }
+    a.part[I.part_base + local] = b;
+    __threadfence();
+    const int t = atomicAdd(&a.ticket[s], 1);
+    last = (t == I.nwg - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // fold the partial boxes of image s
+  int4 b = int4{0x7FFFFFFF, 0x7FFFFFFF, -1, -1};
+  for (int k = threadIdx.x; k < I.nwg; k += kThreads) {
+    const int4 p = a.part[I.part_base + k];
+    b.x = min(b.x, p.x);
+    b.y = min(b.y, p.y);
+    b.z = max(b.z, p.z);
+    b.w = max(b.w, p.w);
+  }
+  b.x = wave_min(b.x);
+  b.y = wave_min(b.y);
+  b.z = wave_max(b.z);
+  b.w = wave_max(b.w);
+  __syncthreads();
+  if (lane == 0) red[wave] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    b = red[0];
+#pragma unroll
+    for (int w = 1; w < kThreads / kWave; ++w) {
+      b.x = min(b.x, red[w].x);
+      b.y = min(b.y, red[w].y);
+      b.z = max(b.z, red[w].z);
+      b.w = max(b.w, red[w].w);
+    }
+    int4 r = int4{0, 0, 0, 0};
+    if (b.z >= 0) r = int4{b.x, b.y, b.z - b.x + 1, b.w - b.y + 1};
+    reinterpret_cast<int4*>(a.roi_out)[s] = r;
+    a.ticket[s] = 0;
+  }
+}
+
+// Rows per workgroup: about 64 KiB of reads per workgroup.
+static int roi_rows(const cmp_image& I, int bpp) {
+  const int64_t row_bytes = (int64_t)(I.roi.w > 0 ? I.roi.w : 1) * bpp;
+  int64_t r = (64 * 1024 + row_bytes - 1) / row_bytes;
+  if (r < 1) r = 1;
+  if (r > I.roi.h) r = I.roi.h > 0 ? I.roi.h : 1;
+  return (int)r;
+}
+
+static int roi_bpp(cmp_format fmt) { return fmt == CMP_RGBA32F ? 16 : fmt == CMP_RGBA16F ? 8 : 4; }
+
+// Workspace: int32 tickets[64] (256 bytes), then one int4 per workgroup.
+static int64_t roi_total_wg(const cmp_image* imgs, int32_t n, cmp_format fmt) {
+  int64_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    const cmp_image& I = imgs[i];
+    if (I.roi.w <= 0 || I.roi.h <= 0) {
+      total += 1;
+      continue;
+    }
+    const int rows = roi_rows(I, roi_bpp(fmt));
+    total += (I.roi.h + rows - 1) / rows;
+  }
+  return total;
+}
+
+}  // namespace cmp
+
+using namespace cmp;
+
+extern "C" size_t cmp_roi_workspace_size(const cmp_image* imgs, int32_t n) {
+  if (n < 0 || (n > 0 && !imgs)) return 0;
+  // the largest of the per-format workgroup counts
+  int64_t wg = roi_total_wg(imgs, n, CMP_RGBA8);
+  const int64_t w2 = roi_total_wg(imgs, n, CMP_RGBA32F), w3 = roi_total_wg(imgs, n, CMP_RGBA16F);
+  if (w2 > wg) wg = w2;
+  if (w3 > wg) wg = w3;
+  return (size_t)(256 + 16 * wg);
+}
+
+extern "C" cmp_status cmp_roi_detect(const cmp_image* imgs, int32_t n, cmp_format fmt,
+                                     int32_t* roi_out_dev, void* workspace, size_t ws_bytes,
+                                     void* stream) {
+  CMP_REQUIRE(n >= 0 && n <= kRoiMax, "n = %d must be 0..%d", n, kRoiMax);
+  if (n == 0) return CMP_OK;
+  CMP_REQUIRE(imgs && roi_out_dev && workspace, "NULL argument");
+  CMP_REQUIRE(((uintptr_t)roi_out_dev & 15) == 0 && ((uintptr_t)workspace & 15) == 0,
+              "roi_out_dev and workspace must be 16-byte aligned");
+  CMP_REQUIRE(fmt == CMP_RGBA8 || fmt == CMP_RGBA32F || fmt == CMP_RGBA16F, "bad format %d", fmt);
+  const int bpp = roi_bpp(fmt);
+  int mode = fmt == CMP_RGBA32F ? 2 : fmt == CMP_RGBA16F ? 3 : 1;
+  if (fmt == CMP_RGBA8) {
+    // all images must agree: depth test or colour test
+    const bool d0 = imgs[0].depth != nullptr;
+    for (int i = 1; i < n; ++i)
+      CMP_REQUIRE((imgs[i].depth != nullptr) == d0,
+                  "either every image has a depth buffer or none has");
+    mode = d0 ? 0 : 1;
+  }
+  RoiArgs a;
+  memset(&a, 0, sizeof a);
+  int64_t wg = 0;
+  for (int i = 0; i < n; ++i) {
+    const cmp_image& I = imgs[i];
+    CMP_REQUIRE(rect_valid(I.roi), "imgs[%d] has a negative size", i);
+    const bool empty = rect_empty(I.roi);
+    if (!empty) {
+      CMP_REQUIRE(mode == 0 ? I.depth != nullptr : I.color != nullptr, "imgs[%d]: NULL buffer", i);
+      CMP_REQUIRE(I.pitch >= I.roi.w, "imgs[%d].pitch < width", i);
+      const uintptr_t p = (uintptr_t)(mode == 0 ? (const void*)I.depth : I.color);
+      CMP_REQUIRE(p % (uintptr_t)(bpp < 16 ? bpp : 16) == 0, "imgs[%d]: misaligned buffer", i);
+    }
+    const int rows = empty ? 1 : roi_rows(I, bpp);
+    const int nwg = empty ? 1 : (I.roi.h + rows - 1) / rows;
+    a.im[i] = RoiImg{I.color, I.depth, I.pitch, empty ? 0 : I.roi.w, empty ? 0 : I.roi.h,
+                     (int32_t)wg, nwg, rows, (int32_t)wg};
+    wg += nwg;
+  }
+  CMP_REQUIRE(wg < (1 << 24), "too many workgroups");
+  const size_t need = (size_t)(256 + 16 * wg);
+  if (ws_bytes < need) {
+    set_error("workspace of %zu bytes is smaller than %zu", ws_bytes, need);
+    return CMP_ENOSPC;
+  }
+  a.roi_out = roi_out_dev;
+  a.ticket = (int32_t*)workspace;
+  a.part = (int4*)((char*)workspace + 256);
+  a.n = n;
+  a.mode = mode;
+  hipStream_t s = (hipStream_t)stream;
+  switch (mode) {
+    case 0: hipLaunchKernelGGL(roi_kernel<0>, dim3((unsigned)wg), dim3(kThreads), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(roi_kernel<1>, dim3((unsigned)wg), dim3(kThreads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(roi_kernel<2>, dim3((unsigned)wg), dim3(kThreads), 0, s, a); break;
+    default: hipLaunchKernelGGL(roi_kernel<3>, dim3((unsigned)wg), dim3(kThreads), 0, s, a); break;
+  }
+  CMP_CHECK_HIP(hipGetLastError());
+  return CMP_OK;
+}

@@ -1,0 +1,560 @@
+"""GPU parity: every entry point of the HIP library against the oracle on the
+same seeded inputs. Integer work (depth compositing, ROI, RLE) must match bit
+for bit; float work within the stated tolerances:
+  over forward:  |x - ref| <= 2e-6 |ref| + 1e-30 per channel, ref = FP64 oracle
+  over backward: |g - ref| <= 2e-6 g_abs + 1e-30, g_abs = the oracle's
+                 componentwise condition scale (G can cancel in the alpha term)
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1902_08755_amd as cmp
+import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+F = 0xFFFFFFFF
+
+
+def note(msg):
+    print(f"[gpu case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def u32(t):
+    return synth.as_u32(t)
+
+
+def _oracle_depth(images, viewport):
+    return oracle.composite_depth([u32(i.color) for i in images], [u32(i.depth) for i in images],
+                                  [i.roi for i in images], viewport)
+
+
+def _close(got, ref, rtol=2e-6):
+    got = np.asarray(got, dtype=np.float64)
+    return np.abs(got - ref) <= rtol * np.abs(ref) + 1e-30
+
+
+# ------------------------------------------------------------------ depth
+SCHEDS = [("seq", 1), ("direct_send", 4), ("direct_send", 7), ("binary_swap", 4),
+          ("binary_swap", 16), ("binary_swap", 64)]
+
+
+def test_depth_rect_workload_all_schedules():
+    """4 x 640x480 contributors with 20 random rectangles each."""
+    note("depth rects 4x640x480")
+    wl = synth.depth_rects(seed=1, n=4, W=640, H=480, device=DEV)
+    ref_c, ref_d = _oracle_depth(wl.images, wl.viewport)
+    for sched in SCHEDS:
+        for tile in [(0, 0), (128, 8), (32, 32), (4, 1)]:
+            oc, od = cmp.composite_depth(wl.images, wl.viewport, schedule=sched, tile=tile)
+            torch.cuda.synchronize()
+            assert (u32(oc) == ref_c).all(), (sched, tile)
+            assert (u32(od) == ref_d).all(), (sched, tile)
+
+
+def _random_depth_images(rng, n, W, H, depth_range, device=DEV):
+    imgs = []
+    for i in range(n):
+        w, h = int(rng.integers(0, W + 3)), int(rng.integers(0, H + 3))
+        x, y = int(rng.integers(-3, W + 2)), int(rng.integers(-3, H + 2))
+        P = w + int(rng.integers(0, 5))
+        d = rng.integers(0, depth_range, size=(h, P), dtype=np.uint64).astype(np.uint32)
+        d[rng.random((h, P)) < 0.15] = F
+        c = rng.integers(0, 2 ** 32, size=(h, P), dtype=np.uint64).astype(np.uint32)
+        imgs.append(cmp.Image(torch.from_numpy(c.view(np.int32)).to(device),
+                              torch.from_numpy(d.view(np.int32)).to(device), (x, y, w, h)))
+    return imgs
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_depth_random_ragged(seed):
+    """Random placements (partly outside), pitches, ties, ragged tiles and
+    viewport offsets; 3..60 contributors (more than one pass above 48)."""
+    rng = np.random.default_rng(seed)
+    n = [3, 5, 9, 17, 33, 49, 60, 2, 1, 0][seed]
+    W, H = int(rng.integers(1, 300)), int(rng.integers(1, 130))
+    imgs = _random_depth_images(rng, n, W, H, depth_range=5 if seed % 2 else 2 ** 32 - 1)
+    vp = (int(rng.integers(-5, 6)), int(rng.integers(-5, 6)), W, H)
+    note(f"depth random seed={seed} n={n} vp={vp}")
+    ref_c, ref_d = _oracle_depth(imgs, vp)
+    for sched in [("seq", 1), ("direct_send", 3), ("binary_swap", 8)]:
+        # a wider output pitch
+        oc = torch.full((H, W + 7), -1, dtype=torch.int32, device=DEV)
+        od = torch.full((H, W + 7), -1, dtype=torch.int32, device=DEV)
+        cmp.composite_depth(imgs, vp, out_color=oc, out_depth=od, schedule=sched, tile=(8, 3))
+        torch.cuda.synchronize()
+        assert (u32(oc[:, :W]) == ref_c).all(), sched
+        assert (u32(od[:, :W]) == ref_d).all(), sched
+        assert (oc[:, W:] == -1).all() and (od[:, W:] == -1).all()   # no write past the row
+
+
+def test_depth_device_roi_override_and_colour_only():
+    rng = np.random.default_rng(77)
+    imgs = _random_depth_images(rng, 6, 90, 50, depth_range=100)
+    # device placements: shifted, shrunk, one negative (empty), one larger than the buffer
+    rois = []
+    for k, im in enumerate(imgs):
+        x, y, w, h = im.roi
+        rois.append([(x + 3, y - 2, w - 1, h, ), (x, y, -4, h), (x, y, w + 10, h + 10)][k % 3])
+    rd = torch.tensor(rois, dtype=torch.int32, device=DEV)
+    eff = [(x, y, max(0, min(w, im.roi[2])), max(0, min(h, im.roi[3])))
+           for (x, y, w, h), im in zip(rois, imgs)]
+    note("depth device roi override")
+    vp = (0, 0, 90, 50)
+    ref_c, ref_d = oracle.composite_depth([u32(i.color) for i in imgs], [u32(i.depth) for i in imgs],
+                                          eff, vp)
+    oc, od = cmp.composite_depth(imgs, vp, roi_dev=rd)
+    oc2, _ = cmp.composite_depth(imgs, vp, roi_dev=rd, want_depth=False)
+    torch.cuda.synchronize()
+    assert (u32(oc) == ref_c).all() and (u32(od) == ref_d).all()
+    assert (u32(oc2) == ref_c).all()
+
+
+def test_depth_repeat_runs_bitwise_equal():
+    """Race canary: repeated launches give identical bits."""
+    wl = synth.depth_ramps_roi(seed=2, n=16, W=1920, H=1080, device=DEV)
+    note("depth repeat 16x1920x1080")
+    first = [t.clone() for t in cmp.composite_depth(wl.images, wl.viewport,
+                                                    schedule=("binary_swap", 16))]
+    for _ in range(3):
+        oc, od = cmp.composite_depth(wl.images, wl.viewport, schedule=("binary_swap", 16))
+        assert torch.equal(oc, first[0]) and torch.equal(od, first[1])
+
+
+# -------------------------------------------------------------------- ROI
+def test_roi_detect_ramp_images_exact():
+    """16 full-frame 1920x1080 contributors; the generator knows each ROI."""
+    wl = synth.depth_ramps_full(seed=2, n=16, W=1920, H=1080, device=DEV)
+    note("roi 16x1920x1080")
+    roi = cmp.roi_detect(wl.images)
+    torch.cuda.synchronize()
+    got = [tuple(r) for r in roi.cpu().tolist()]
+    assert got == [im.true_roi for im in wl.images]
+    # and the oracle on two of them
+    for k in (0, 7):
+        assert got[k] == oracle.roi_detect_depth(u32(wl.images[k].depth))
+    # repeated calls reuse the workspace (it is left zeroed)
+    for _ in range(3):
+        assert [tuple(r) for r in cmp.roi_detect(wl.images).cpu().tolist()] == got
+
+
+@pytest.mark.parametrize("fmt", ["depth", "rgba8", "f32", "f16"])
+def test_roi_detect_random_formats(fmt):
+    rng = np.random.default_rng({"depth": 1, "rgba8": 2, "f32": 3, "f16": 4}[fmt])
+    imgs, refs = [], []
+    shapes = [(1, 1), (3, 5), (17, 64), (130, 257), (64, 1), (9, 1000), (50, 50), (50, 50)]
+    for k, (h, w) in enumerate(shapes):
+        P = w + (k % 3) * 4
+        m = rng.random((h, P)) < [0.0, 0.5, 0.01, 0.0005, 0.2, 0.001, 1.0, 0.0][k]
+        if k == 3:
+            m[h - 1, w - 1] = True     # a single corner pixel
+        if fmt in ("depth", "rgba8"):
+            v = np.where(m, rng.integers(0, F - 1, (h, P), dtype=np.uint64), F if fmt == "depth" else 0)
+            a = v.astype(np.uint32)
+            t = torch.from_numpy(a.view(np.int32)).to(DEV)
+            img = cmp.Image(t, t if fmt == "depth" else None, (0, 0, w, h))
+            refs.append(oracle.roi_detect_depth(a, w, h) if fmt == "depth" else oracle.roi_detect_rgba8(a, w, h))
+        else:
+            L = np.zeros((h, P, 4), np.float32)
+            L[m, k % 4] = rng.random(m.sum()).astype(np.float32) + 0.25
+            L[~m, 0] = -0.0          # negative zero is empty
+            if k == 5:
+                L[0, 0, 2] = np.nan  # NaN is data
+            L = L.astype(np.float16 if fmt == "f16" else np.float32)
+            img = cmp.Image(torch.from_numpy(L).to(DEV), None, (0, 0, w, h))
+            refs.append(oracle.roi_detect_rgbaf(L, w, h))
+        imgs.append(img)
+    note(f"roi formats {fmt}")
+    f = {"depth": cmp.RGBA8, "rgba8": cmp.RGBA8, "f32": cmp.RGBA32F, "f16": cmp.RGBA16F}[fmt]
+    roi = cmp.roi_detect(imgs, fmt=f)
+    torch.cuda.synchronize()
+    assert [tuple(r) for r in roi.cpu().tolist()] == refs
+
+
+# -------------------------------------------------------------------- RLE
+def _check_streams(imgs, rois, streams, sizes):
+    for k, im in enumerate(imgs):
+        c, d = u32(im.color), (u32(im.depth) if im.depth is not None else None)
+        ref = oracle.rle_compress(c, d, rois[k])
+        n = int(sizes[k])
+        assert n == ref.size, (k, n, ref.size)
+        assert (streams[k][:n].cpu().numpy() == ref).all(), k
+
+
+def test_rle_rect_composite_round_trip():
+    """RLE of the composite of the 640x480 rectangle workload, ROI from the GPU."""
+    wl = synth.depth_rects(seed=1, n=4, W=640, H=480, device=DEV)
+    oc, od = cmp.composite_depth(wl.images, wl.viewport)
+    full = cmp.Image(oc, od, (0, 0, 640, 480))
+    roi = cmp.roi_detect([full])
+    note("rle rect composite")
+    streams, sizes = cmp.rle_compress([full], roi_dev=roi)
+    torch.cuda.synchronize()
+    r = tuple(roi[0].tolist())
+    _check_streams([full], [r], streams, sizes)
+    outc = torch.zeros((480, 640), dtype=torch.int32, device=DEV)
+    outd = torch.zeros((480, 640), dtype=torch.int32, device=DEV)
+    ro, st = cmp.rle_decompress([streams[0]], [cmp.Image(outc, outd, (0, 0, 640, 480))])
+    torch.cuda.synchronize()
+    assert int(st[0]) == 0 and tuple(ro[0].tolist()) == r
+    x, y, w, h = r
+    # the ROI block lands at the top left of the destination, in its pitch
+    assert torch.equal(outc[:h, :w], oc[y:y + h, x:x + w])
+    assert torch.equal(outd[:h, :w], od[y:y + h, x:x + w])
+
+
+def test_rle_adversarial_images():
+    """Runs of 255/256/257, noise, single pixels, one-block and block+1 ROIs,
+    empty ROIs, 4-plane (colour-only) images, several images per launch."""
+    rng = np.random.default_rng(5)
+    specs = [((1, 1), (0, 0, 1, 1)), ((130, 150), (7, 3, 129, 101)), ((64, 128), (0, 0, 128, 32)),
+             ((65, 64), (0, 0, 64, 65)), ((20, 30), (5, 5, 0, 7)), ((300, 301), (0, 0, 301, 300)),
+             ((40, 4100), (1, 2, 4097, 3)), ((33, 33), (32, 32, 1, 1))]
+    imgs, rois, mk = [], [], []
+    for k, ((H, W), roi) in enumerate(specs):
+        c = np.zeros((H, W), np.uint32)
+        d = np.full((H, W), F, np.uint32)
+        flat, dflat = c.reshape(-1), d.reshape(-1)
+        pos = 0
+        for run in [255, 256, 257, 1, 1, 2, 511, 513, 4095, 4096, 4097]:
+            if pos >= flat.size:
+                break
+            flat[pos:pos + run] = rng.integers(0, 2 ** 32, dtype=np.uint64)
+            dflat[pos:pos + run] = rng.integers(0, 2 ** 32, dtype=np.uint64)
+            pos = min(flat.size, pos + run)
+        k2 = min(flat.size, pos + 3000)
+        flat[pos:k2] = rng.integers(0, 2 ** 32, k2 - pos, dtype=np.uint64).astype(np.uint32)
+        tc = torch.from_numpy(c.view(np.int32)).to(DEV)
+        td = torch.from_numpy(d.view(np.int32)).to(DEV)
+        imgs.append(cmp.Image(tc, td if k % 3 else None, (0, 0, W, H)))
+        rois.append(roi)
+    rd = torch.tensor(rois, dtype=torch.int32, device=DEV)
+    note("rle adversarial")
+    batch = cmp.RleBatch(imgs, roi_dev=rd)
+    for rep in range(3):          # the workspace is reused: epochs, tickets
+        streams, sizes = batch.run()
+        torch.cuda.synchronize()
+        assert int(batch.status.abs().sum()) == 0
+        _check_streams(imgs, [r if r[2] * r[3] else (0, 0, 0, 0) for r in rois], streams, sizes)
+    # decode all at once into full-size buffers
+    outs = [cmp.Image(torch.zeros_like(im.color), None if im.depth is None else torch.zeros_like(im.depth),
+                      im.roi) for im in imgs]
+    ro, st = cmp.rle_decompress(streams, outs)
+    torch.cuda.synchronize()
+    assert (st == 0).all()
+    for im, o, (x, y, w, h) in zip(imgs, outs, rois):
+        if w * h == 0:
+            continue
+        assert torch.equal(o.color[:h, :w], im.color[y:y + h, x:x + w])
+        if im.depth is not None:
+            assert torch.equal(o.depth[:h, :w], im.depth[y:y + h, x:x + w])
+
+
+def test_rle_decompress_rejects_corrupt_streams():
+    depth = np.array([[5, 5, F], [5, 3, F], [F, F, F], [F, F, 7]], np.uint32)
+    color = np.where(depth != F, 0xFF332211, 0).astype(np.uint32)
+    good = oracle.rle_compress(color, depth, (0, 0, 3, 4))
+    cases = {"magic": (0, 0x53), "nplanes": (20, 5), "block": (25, 0x20), "nblocks": (28, 2),
+             "boff": (32, 16), "odd": (36, 11), "toolong": (36, 13), "overflow": (80, 5),
+             "short": (80, 0)}
+    streams, names = [], []
+    for name, (pos, val) in cases.items():
+        s = good.copy()
+        s[pos] = val
+        streams.append(torch.from_numpy(s).to(DEV))
+        names.append(name)
+    streams.append(torch.from_numpy(good).to(DEV))
+    names.append("good")
+    outs = [cmp.Image(torch.zeros((4, 3), dtype=torch.int32, device=DEV),
+                      torch.zeros((4, 3), dtype=torch.int32, device=DEV), (0, 0, 3, 4))
+            for _ in streams]
+    # a too-small destination and a missing depth buffer: CMP_ENOSPC
+    streams += [torch.from_numpy(good).to(DEV)] * 2
+    names += ["small", "nodepth"]
+    outs.append(cmp.Image(torch.zeros((4, 3), dtype=torch.int32, device=DEV),
+                          torch.zeros((4, 3), dtype=torch.int32, device=DEV), (0, 0, 2, 4)))
+    outs.append(cmp.Image(torch.zeros((4, 3), dtype=torch.int32, device=DEV), None, (0, 0, 3, 4)))
+    note("rle corrupt")
+    _, st = cmp.rle_decompress(streams, outs)
+    torch.cuda.synchronize()
+    st = st.cpu().tolist()
+    for name, s in zip(names, st):
+        if name == "good":
+            assert s == 0
+        elif name in ("small", "nodepth"):
+            assert s == cmp.CMP_ENOSPC, name
+        else:
+            assert s == cmp.CMP_ECORRUPT, name
+    assert (u32(outs[names.index("good")].color) == color).all()
+
+
+# ------------------------------------------------------------------- over
+def _over_layers(rng, n, W, H, dtype, full=False):
+    layers = []
+    for _ in range(n):
+        if full:
+            x, y, w, h = 0, 0, W, H
+        else:
+            w, h = int(rng.integers(1, W + 1)), int(rng.integers(1, H + 1))
+            x, y = int(rng.integers(-2, W)), int(rng.integers(-2, H))
+        P = w + int(rng.integers(0, 3))
+        a = rng.beta(2, 5, size=(h, P))
+        L = np.empty((h, P, 4))
+        L[..., :3] = rng.random((h, P, 3)) * a[..., None]
+        L[..., 3] = a
+        layers.append(cmp.Image(torch.from_numpy(L.astype(dtype)).to(DEV), None, (x, y, w, h)))
+    return layers
+
+
+def _np(l):
+    return l.color.cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+@pytest.mark.parametrize("seed", range(4))
+def test_over_random(dtype, seed):
+    rng = np.random.default_rng(200 + seed)
+    n = [1, 7, 13, 70][seed]
+    W, H = int(rng.integers(1, 200)), int(rng.integers(1, 90))
+    layers = _over_layers(rng, n, W, H, dtype)
+    order = list(rng.permutation(n))
+    vp = (int(rng.integers(-2, 3)), int(rng.integers(-2, 3)), W, H)
+    note(f"over random seed={seed} n={n} dtype={dtype.__name__}")
+    ref = oracle.composite_over([_np(l) for l in layers], [l.roi for l in layers], order, vp)
+    seq = cmp.composite_over(layers, order, vp, tile=(16, 4))
+    ds = cmp.composite_over(layers, order, vp, schedule=("direct_send", 5), tile=(64, 1))
+    torch.cuda.synchronize()
+    assert _close(seq.cpu().numpy(), ref).all()
+    assert torch.equal(seq, ds)               # same per-pixel chain, same bits
+    if n <= 64:
+        for P in (2, 4, 16):
+            bs = cmp.composite_over(layers, order, vp, schedule=("binary_swap", P))
+            tref = oracle.composite_over([_np(l) for l in layers], [l.roi for l in layers], order,
+                                         vp, groups=P)
+            torch.cuda.synchronize()
+            assert _close(bs.cpu().numpy(), tref).all(), P
+            # tree and sequential agree within 1e-6 in FP32
+            s = seq.cpu().numpy().astype(np.float64)
+            assert (np.abs(bs.cpu().numpy() - s) <= 1e-6 * np.abs(s) + 1e-30).all()
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
+def test_over_bricks_full_size_sampled(dtype):
+    """64 layers at 3840x2160 (the brick workload); sampled pixels against the
+    oracle, computed pixel by pixel on the sampled positions only."""
+    note(f"over bricks 64x3840x2160 {dtype}")
+    ow = synth.over_bricks(seed=3, n=64, W=3840, H=2160, device=DEV, dtype=dtype)
+    out = cmp.composite_over(ow.layers, ow.order, ow.viewport)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(9)
+    ys = np.concatenate([rng.integers(0, 2160, 200), [0, 2159, 1080]])
+    xs = np.concatenate([rng.integers(0, 3840, 200), [0, 3839, 1]])
+    idx_y = torch.from_numpy(ys).to(DEV)
+    idx_x = torch.from_numpy(xs).to(DEV)
+    samp = [l.rgba[idx_y, idx_x].cpu().numpy().reshape(1, -1, 4) for l in ow.layers]
+    ref = oracle.composite_over(samp, [(0, 0, len(xs), 1)] * 64, ow.order, (0, 0, len(xs), 1))[0]
+    got = out[idx_y, idx_x].cpu().numpy()
+    ok = _close(got, ref)
+    assert ok.all(), np.abs(got - ref).max()
+    # the whole frame: finite, premultiplied (alpha in [0, 1])
+    assert torch.isfinite(out).all() and float(out[..., 3].max()) <= 1.0
+
+
+# --------------------------------------------------------------- backward
+def _bwd_check(layers, order, vp, G):
+    grads = cmp.composite_over_backward(layers, order, vp, torch.from_numpy(G.astype(np.float32)).to(DEV))
+    torch.cuda.synchronize()
+    ref, scale = oracle.composite_over_backward([_np(l) for l in layers], [l.roi for l in layers],
+                                                order, vp, G.astype(np.float32).astype(np.float64),
+                                                want_scale=True)
+    for k, (g, r, s) in enumerate(zip(grads, ref, scale)):
+        w = layers[k].roi[2]
+        got = g.cpu().numpy().astype(np.float64)
+        bad = np.abs(got - r[:, :w]) > 2e-6 * s[:, :w] + 1e-30
+        assert not bad.any(), (k, np.abs(got - r[:, :w]).max())
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_over_backward_random(seed):
+    rng = np.random.default_rng(300 + seed)
+    n = [1, 5, 32, 50][seed]
+    W, H = int(rng.integers(1, 150)), int(rng.integers(1, 70))
+    layers = _over_layers(rng, n, W, H, np.float32 if seed % 2 else np.float16)
+    order = list(rng.permutation(n))
+    vp = (int(rng.integers(-2, 3)), int(rng.integers(-2, 3)), W, H)
+    G = rng.standard_normal((H, W, 4))
+    note(f"over backward seed={seed} n={n}")
+    _bwd_check(layers, order, vp, G)
+
+
+def test_over_backward_grad_target_workload():
+    """32 layers at 1024x1024 with loss = sum (out - t)^2 (G = 2 (out - t)):
+    every gradient element against the FP64 adjoint."""
+    note("over backward 32x1024x1024")
+    ow = synth.over_bricks(seed=4, n=32, W=1024, H=1024, device=DEV, with_target=True)
+    layers = [l.rgba.requires_grad_(True) for l in ow.layers]
+    rois = [l.roi for l in ow.layers]
+    out = cmp.OverComposite.apply(ow.order, ow.viewport, rois, *layers)
+    loss = ((out - ow.target) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    G = (2.0 * (out.detach() - ow.target)).cpu().numpy().astype(np.float64)
+    Ls = [l.detach().cpu().numpy() for l in layers]
+    ref, scale = oracle.composite_over_backward(Ls, rois, ow.order, ow.viewport, G, want_scale=True)
+    for k in range(32):
+        got = layers[k].grad.cpu().numpy().astype(np.float64)
+        assert not (np.abs(got - ref[k]) > 2e-6 * scale[k] + 1e-30).any(), k
+    # forward against the oracle on a band of rows
+    ref_out = oracle.composite_over([L[:64] for L in Ls], [(0, 0, 1024, 64)] * 32, ow.order,
+                                    (0, 0, 1024, 64))
+    assert _close(out.detach()[:64].cpu().numpy(), ref_out).all()
+
+
+# ------------------------------------------------------------------ batch
+def _cjobs(jobs, outs):
+    keep = []
+    arr = (cmp.CJob * len(jobs))()
+    for k, (job, out) in enumerate(zip(jobs, outs)):
+        wl = job.work
+        if job.kind == "depth":
+            imgs = cmp._images(wl.images, "u32")
+            arr[k] = cmp.CJob(0, cmp.RGBA8, len(wl.images), imgs, None, cmp._rect(wl.viewport),
+                              out[0].data_ptr(), out[1].data_ptr(), out[0].stride(0))
+            keep.append(imgs)
+        else:
+            imgs = cmp._images(wl.layers, "rgba")
+            import ctypes
+            order = (ctypes.c_int32 * len(wl.order))(*wl.order)
+            arr[k] = cmp.CJob(1, cmp.RGBA32F, len(wl.layers), imgs, order, cmp._rect(wl.viewport),
+                              out.data_ptr(), None, out.stride(0) // 4)
+            keep += [imgs, order]
+    return arr, keep
+
+
+def _alloc_outs(jobs):
+    outs = []
+    for job in jobs:
+        _, _, w, h = job.work.viewport
+        if job.kind == "depth":
+            outs.append((torch.full((h, w), 7, dtype=torch.int32, device=DEV),
+                         torch.full((h, w), 7, dtype=torch.int32, device=DEV)))
+        else:
+            outs.append(torch.full((h, w, 4), 7.0, dtype=torch.float32, device=DEV))
+    return outs
+
+
+def test_batch_persistent_equals_plain_and_oracle():
+    import ctypes
+    jobs = synth.batch_jobs(seed=5, njobs=24, device=DEV, log2_range=(3.0, 8.0), n_range=(2, 9))
+    outs_a, outs_b = _alloc_outs(jobs), _alloc_outs(jobs)
+    arr_a, keep_a = _cjobs(jobs, outs_a)
+    arr_b, keep_b = _cjobs(jobs, outs_b)
+    L = cmp.lib()
+    plan_a, plan_b = ctypes.c_void_p(), ctypes.c_void_p()
+    assert L.cmp_batch_plan_create(arr_a, len(jobs), None, ctypes.byref(plan_a)) == 0
+    assert L.cmp_batch_plan_create(arr_b, len(jobs), None, ctypes.byref(plan_b)) == 0
+    ws = torch.zeros(L.cmp_batch_workspace_size(plan_a) + 64, dtype=torch.uint8, device=DEV)
+    s = torch.cuda.current_stream().cuda_stream
+    note("batch 24 jobs")
+    assert L.cmp_batch_upload(plan_a, ws.data_ptr(), ws.numel(), s) == 0
+    torch.cuda.synchronize()
+    for rep in range(3):   # the queue resets itself between launches
+        assert L.cmp_batch_run(plan_a, ws.data_ptr(), s) == 0
+    assert L.cmp_batch_run_plain(plan_b, s) == 0
+    torch.cuda.synchronize()
+    for job, a, b in zip(jobs, outs_a, outs_b):
+        if job.kind == "depth":
+            assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+        else:
+            assert torch.equal(a, b)
+    for job, a in list(zip(jobs, outs_a))[:6]:
+        wl = job.work
+        if job.kind == "depth":
+            rc, rd = _oracle_depth(wl.images, wl.viewport)
+            assert (u32(a[0]) == rc).all() and (u32(a[1]) == rd).all()
+        else:
+            ref = oracle.composite_over([_np(l) if hasattr(l, 'color') else l.rgba.cpu().numpy()
+                                         for l in wl.layers], [l.roi for l in wl.layers], wl.order,
+                                        wl.viewport)
+            assert _close(a.cpu().numpy(), ref).all()
+    L.cmp_batch_plan_destroy(plan_a)
+    L.cmp_batch_plan_destroy(plan_b)
+    del keep_a, keep_b
+
+
+def test_batch_graph_replay():
+    """The persistent launch captured in a HIP graph and replayed several times,
+    with eager work in between; every replay matches the eager result."""
+    import ctypes
+    jobs = synth.batch_jobs(seed=6, njobs=12, device=DEV, log2_range=(4.0, 8.0), n_range=(2, 6))
+    outs = _alloc_outs(jobs)
+    arr, keep = _cjobs(jobs, outs)
+    L = cmp.lib()
+    plan = ctypes.c_void_p()
+    assert L.cmp_batch_plan_create(arr, len(jobs), None, ctypes.byref(plan)) == 0
+    ws = torch.zeros(L.cmp_batch_workspace_size(plan) + 64, dtype=torch.uint8, device=DEV)
+    stream = torch.cuda.Stream()
+    note("batch graph replay")
+    with torch.cuda.stream(stream):
+        assert L.cmp_batch_upload(plan, ws.data_ptr(), ws.numel(), stream.cuda_stream) == 0
+        assert L.cmp_batch_run(plan, ws.data_ptr(), stream.cuda_stream) == 0
+    stream.synchronize()
+    eager = [tuple(t.clone() for t in o) if isinstance(o, tuple) else o.clone() for o in outs]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        assert L.cmp_batch_run(plan, ws.data_ptr(), stream.cuda_stream) == 0
+    for rep in range(4):
+        for o in outs:   # scribble, then replay
+            (o[0] if isinstance(o, tuple) else o).fill_(3)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, e in zip(outs, eager):
+            if isinstance(o, tuple):
+                assert torch.equal(o[0], e[0]) and torch.equal(o[1], e[1])
+            else:
+                assert torch.equal(o, e)
+    L.cmp_batch_plan_destroy(plan)
+    del keep
+
+
+# --------------------------------------------------------- whole pipeline
+def test_ramp_pipeline_full_size():
+    """16 x 1920x1080: roi_detect -> RLE compress -> decompress -> depth
+    compositing (binary swap over 16 owners), against the oracle chain."""
+    note("pipeline 16x1920x1080")
+    wl = synth.depth_ramps_full(seed=2, n=16, W=1920, H=1080, device=DEV)
+    roi = cmp.roi_detect(wl.images)
+    batch = cmp.RleBatch(wl.images, roi_dev=roi)
+    streams, sizes = batch.run()
+    blocks = [cmp.Image(torch.zeros((1080, 1920), dtype=torch.int32, device=DEV),
+                        torch.zeros((1080, 1920), dtype=torch.int32, device=DEV), (0, 0, 1920, 1080))
+              for _ in range(16)]
+    ro, st = cmp.rle_decompress(streams, blocks)
+    placed = [cmp.Image(b.color, b.depth, (0, 0, 1920, 1080)) for b in blocks]
+    oc, od = cmp.composite_depth(placed, wl.viewport, roi_dev=ro, schedule=("binary_swap", 16))
+    torch.cuda.synchronize()
+    assert (st == 0).all() and int(batch.status.abs().sum()) == 0
+    # oracle chain
+    rois = [oracle.roi_detect_depth(u32(im.depth)) for im in wl.images]
+    assert [tuple(r) for r in roi.cpu().tolist()] == rois
+    crops_c, crops_d = [], []
+    for k, im in enumerate(wl.images):
+        c, d = u32(im.color), u32(im.depth)
+        ref = oracle.rle_compress(c, d, rois[k])
+        n = int(sizes[k])
+        assert n == ref.size and (streams[k][:n].cpu().numpy() == ref).all(), k
+        r2, c2, d2 = oracle.rle_decompress(ref)
+        crops_c.append(c2)
+        crops_d.append(d2)
+    ref_c, ref_d = oracle.composite_depth(crops_c, crops_d, rois, wl.viewport)
+    assert (u32(oc) == ref_c).all() and (u32(od) == ref_d).all()
+    # cropping is lossless: the same as compositing the full frames
+    full_c, full_d = _oracle_depth(wl.images, wl.viewport)
+    assert (ref_c == full_c).all() and (ref_d == full_d).all()

@@ -212,14 +212,15 @@ def test_round_trip_and_structure(shape, roi):
         s = oracle.rle_compress(c, depth, roi)
         assert s.size <= oracle.rle_max_size(roi[2], roi[3], 8 if depth is not None else 4)
         p = parse_rle1(s.tobytes())
-        assert p.roi == roi
+        assert p.roi == (roi if roi[2] * roi[3] else (0, 0, 0, 0))
         assert p.planes == _planes_of(c, depth, roi)
         r, c2, d2 = oracle.rle_decompress(s)
         x, y, w, h = roi
-        assert r == roi
-        assert (c2 == c[y:y + h, x:x + w]).all()
+        # an empty ROI is stored in its canonical form (0, 0, 0, 0)
+        assert r == (roi if w * h else (0, 0, 0, 0))
+        assert c2.size == w * h and (c2.reshape(-1) == c[y:y + h, x:x + w].reshape(-1)).all()
         if depth is not None:
-            assert (d2 == d[y:y + h, x:x + w]).all()
+            assert d2.size == w * h and (d2.reshape(-1) == d[y:y + h, x:x + w].reshape(-1)).all()
         else:
             assert d2 is None
 
