@@ -145,9 +145,9 @@ def time_graph(frames, steps, s_obj):
     graphs = []
     for f in frames:
         g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=s_obj):
+        with torch.cuda.graph(g):   # captured on torch's side stream
             for k in range(4):
-                f.stage(k, s_obj.cuda_stream)
+                f.stage(k, torch.cuda.current_stream().cuda_stream)
         graphs.append(g)
     torch.cuda.synchronize()
     for g in graphs:

@@ -1,8 +1,10 @@
 // Batched compositing: many uneven jobs in one persistent launch.
 //
-// The plan flattens every job into workgroup tiles ("work items"), orders the
-// items largest first (longest-processing-time order, so the big items start
-// early and small ones fill the tail) and uploads the job records,
+// The plan cuts every job into workgroup tiles, groups runs of consecutive
+// tiles into work items of about kItemBytes of traffic (so the shared queue
+// counter is touched rarely), orders the items largest first
+// (longest-processing-time order: big items start early, small ones fill the
+// tail) and uploads the job records,
 // contributor descriptors and items to the caller's workspace. The kernel's
 // workgroups, sized to fill the GPU once, pull items from an atomic queue
 // counter until it runs dry, like render clients pulling tile work packages
@@ -42,7 +44,7 @@ struct JobRec {
 };
 
 struct Item {
-  int32_t job, tile;
+  int32_t job, tile0, ntiles, pad;   // tiles [tile0, tile0 + ntiles) of one job
 };
 
 struct BatchArgs {
@@ -65,20 +67,22 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const BatchArgs a) {
     if (it >= a.nitems) break;
     const Item I = a.items[it];
     const JobRec& J = a.jobs[uniform(I.job)];
-    const int tile = uniform(I.tile);
-    const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
-    const int x0 = J.vx + tx * J.tile_w, y0 = J.vy + ty * J.tile_h;
-    const int tw = min(J.tile_w, J.vx + J.vw - x0), th = min(J.tile_h, J.vy + J.vh - y0);
-    if (J.kind == 0) {
-      const DepthSrc src{a.ddesc + J.desc_off, nullptr, 0};
-      depth_tile(src, J.n, x0, y0, tw, th, (uint32_t*)J.out_color, J.out_depth, J.out_pitch, J.vx,
-                 J.vy, false);
-    } else if (J.fmt == CMP_RGBA32F) {
-      over_tile_seq<CMP_RGBA32F>(a.odesc + J.desc_off, J.n, x0, y0, tw, th, (float*)J.out_color,
-                                 J.out_pitch, J.vx, J.vy, false);
-    } else {
-      over_tile_seq<CMP_RGBA16F>(a.odesc + J.desc_off, J.n, x0, y0, tw, th, (float*)J.out_color,
-                                 J.out_pitch, J.vx, J.vy, false);
+    const int t1 = uniform(I.tile0) + uniform(I.ntiles);
+    for (int tile = uniform(I.tile0); tile < t1; ++tile) {
+      const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
+      const int x0 = J.vx + tx * J.tile_w, y0 = J.vy + ty * J.tile_h;
+      const int tw = min(J.tile_w, J.vx + J.vw - x0), th = min(J.tile_h, J.vy + J.vh - y0);
+      if (J.kind == 0) {
+        const DepthSrc src{a.ddesc + J.desc_off, nullptr, 0};
+        depth_tile(src, J.n, x0, y0, tw, th, (uint32_t*)J.out_color, J.out_depth, J.out_pitch,
+                   J.vx, J.vy, false);
+      } else if (J.fmt == CMP_RGBA32F) {
+        over_tile_seq<CMP_RGBA32F>(a.odesc + J.desc_off, J.n, x0, y0, tw, th, (float*)J.out_color,
+                                   J.out_pitch, J.vx, J.vy, false);
+      } else {
+        over_tile_seq<CMP_RGBA16F>(a.odesc + J.desc_off, J.n, x0, y0, tw, th, (float*)J.out_color,
+                                   J.out_pitch, J.vx, J.vy, false);
+      }
     }
   }
   if (tid == 0) {
@@ -95,9 +99,12 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const BatchArgs a) {
 struct TileShape {
   int w, h;
 };
-static const TileShape kDepthTiles[] = {{64, 16}, {128, 8}, {256, 4}, {32, 32}, {64, 4}};
-static const TileShape kOverTiles[] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}, {64, 8}, {16, 16}};
-static const TileShape kDepthDefault = {64, 16}, kOverDefault = {64, 4};
+static const TileShape kDepthTiles[] = {{64, 16}, {128, 8}, {256, 4}, {32, 32}, {64, 32},
+                                        {128, 16}, {256, 16}};
+static const TileShape kOverTiles[] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}, {64, 8},
+                                       {16, 16}, {64, 16}, {128, 8}};
+static const TileShape kDepthDefault = {64, 16}, kOverDefault = {64, 8};
+constexpr double kItemBytes = 512.0 * 1024.0;   // target traffic of one work item
 
 static int ilog2(int64_t v) {
   int r = 0;
@@ -226,6 +233,16 @@ extern "C" cmp_status cmp_batch_plan_create(const cmp_job* jobs, int32_t njobs,
     int64_t cost;
   };
   std::vector<Cand> cands;
+  // estimated bytes per pixel of a job: every contributor's share of the
+  // viewport it covers, plus the output
+  auto px_bytes = [](const cmp_job& j) -> double {
+    const double area = (double)std::max(1, j.viewport.w) * std::max(1, j.viewport.h);
+    double cover = 0;
+    for (int k = 0; k < j.n; ++k)
+      if (!rect_empty(j.in[k].roi)) cover += (double)j.in[k].roi.w * j.in[k].roi.h;
+    const double per = j.kind == 0 ? 4.0 : (j.fmt == CMP_RGBA32F ? 16.0 : 8.0);
+    return per * cover / area + (j.kind == 0 ? 12.0 : 16.0);
+  };
   for (int i = 0; i < njobs; ++i) {
     const cmp_job& j = jobs[i];
     P->ins.emplace_back(j.in, j.in + j.n);
@@ -269,14 +286,16 @@ extern "C" cmp_status cmp_batch_plan_create(const cmp_job* jobs, int32_t njobs,
       }
     }
     recs.push_back(r);
+    // work items: runs of consecutive tiles worth about kItemBytes of traffic,
+    // so the shared queue counter is touched rarely
     const int tiles_y = r.vh ? (r.vh + t.h - 1) / t.h : 0;
-    for (int ty = 0; ty < tiles_y; ++ty)
-      for (int tx = 0; tx < r.tiles_x; ++tx) {
-        const int tw = std::min(t.w, r.vw - tx * t.w), th = std::min(t.h, r.vh - ty * t.h);
-        // cost: pixels times contributors (bytes read grow with both)
-        cands.push_back(Cand{Item{i, ty * r.tiles_x + tx},
-                             (int64_t)tw * th * (j.n > 0 ? j.n : 1) * (j.kind == 1 ? 4 : 1)});
-      }
+    const int ntiles = tiles_y * r.tiles_x;
+    const double tile_bytes = px_bytes(j) * t.w * t.h;
+    const int per_item = std::max(1, (int)(kItemBytes / std::max(1.0, tile_bytes)));
+    for (int t0 = 0; t0 < ntiles; t0 += per_item) {
+      const int cnt = std::min(per_item, ntiles - t0);
+      cands.push_back(Cand{Item{i, t0, cnt, 0}, (int64_t)(cnt * tile_bytes)});
+    }
   }
   std::stable_sort(cands.begin(), cands.end(),
                    [](const Cand& x, const Cand& y) { return x.cost > y.cost; });

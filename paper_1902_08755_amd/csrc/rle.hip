@@ -303,39 +303,53 @@ __global__ __launch_bounds__(kThreads) void rle_compress_kernel(const RleCArgs a
       }
       if (tid < (int)(padded - total)) stage[total + tid] = 0;
 
-      // ---- decoupled look-back for the payload offset
-      if (tid == 0) {
+      // ---- decoupled look-back for the payload offset: wave 0 reads the
+      // flags of 64 predecessors at once, sums the aggregates up to the
+      // nearest inclusive prefix, and moves the window back if it has none
+      if (tid < kWave) {
         uint64_t* flags = a.flags + I.flag_base;
+        const uint32_t ep = epoch & 0x3FFFFFFFu;
         uint32_t excl = 0;
         if (b == 0) {
-          __hip_atomic_store(&flags[0], mkflag(epoch, kIncl, padded), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+          if (lane == 0)
+            __hip_atomic_store(&flags[0], mkflag(epoch, kIncl, padded), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         } else {
-          __hip_atomic_store(&flags[b], mkflag(epoch, kAgg, padded), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-          int p = b - 1;
+          if (lane == 0)
+            __hip_atomic_store(&flags[b], mkflag(epoch, kAgg, padded), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+          int top = b - 1;   // lane l reads predecessor top - l
           uint32_t spins = 0;
           while (true) {
-            const uint64_t f =
-                __hip_atomic_load(&flags[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t fe = (uint32_t)(f >> 34);
+            const int p = top - lane;
+            uint64_t f = mkflag(epoch, kIncl, 0);   // before block 0: an empty prefix
+            if (p >= 0) f = __hip_atomic_load(&flags[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint64_t st = (f >> 32) & 3u;
-            if (fe != (epoch & 0x3FFFFFFFu) || st == 0) {
-              if (++spins > (1u << 22)) {
-                if (a.status) a.status[s] = CMP_ETIMEOUT;
+            const bool ready = ((uint32_t)(f >> 34) == ep) && st != 0;
+            const uint64_t incl = __ballot(ready && st == kIncl);
+            const uint64_t notready = __ballot(!ready);
+            const int first = incl ? __builtin_ctzll(incl) : kWave;
+            const uint64_t need = first >= kWave - 1 ? ~0ull : ((2ull << first) - 1ull);
+            if (notready & need) {
+              if (++spins > (1u << 20)) {
+                if (lane == 0 && a.status) a.status[s] = CMP_ETIMEOUT;
                 break;
               }
               __builtin_amdgcn_s_sleep(1);
               continue;
             }
-            excl += (uint32_t)f;
-            if (st == kIncl || p == 0) break;
-            --p;
+            uint32_t v = lane <= first ? (uint32_t)f : 0u;
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+            excl += v;
+            if (first < kWave) break;
+            top -= kWave;
           }
-          __hip_atomic_store(&flags[b], mkflag(epoch, kIncl, excl + padded), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+          if (lane == 0)
+            __hip_atomic_store(&flags[b], mkflag(epoch, kIncl, excl + padded), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_excl = excl;
+        if (lane == 0) s_excl = excl;
       }
       __syncthreads();
       const uint32_t excl = s_excl;
@@ -401,10 +415,10 @@ static_assert(sizeof(RleDArgs) <= 4096, "kernel arguments must fit in 4 KiB");
 __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t stage[kStage];
   __shared__ uint16_t ends[kBlock / 2];
+  __shared__ __attribute__((aligned(16))) uint8_t plane_buf[kBlock];
   __shared__ uint64_t sh[8];
-  __shared__ uint32_t s_hdr[8];
   __shared__ uint32_t s_size[8];
-  __shared__ uint32_t s_boff;
+  __shared__ uint32_t s_boff, s_next;
   __shared__ int32_t s_err;
   const int tid = threadIdx.x;
   const int blk = blockIdx.x;
@@ -413,63 +427,62 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
   const RleDImg I = a.im[s];
   const int b = blk - I.wg_begin;
 
-  // ---- header and this block's table entries
-  if (tid == 0) {
-    int err = 0;
-    uint32_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (I.in_bytes < 32) {
+  // ---- header (every lane reads it: one broadcast load) and this block's
+  // table entries (one lane per entry)
+  uint32_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int err = 0;
+  if (I.in_bytes < 32) {
+    err = CMP_ECORRUPT;
+  } else {
+    const u32x4 h0 = reinterpret_cast<const u32x4*>(I.in)[0];
+    const u32x4 h1 = reinterpret_cast<const u32x4*>(I.in)[1];
+    h[0] = h0.x; h[1] = h0.y; h[2] = h0.z; h[3] = h0.w;
+    h[4] = h1.x; h[5] = h1.y; h[6] = h1.z; h[7] = h1.w;
+    const int32_t w = (int32_t)h[3], hh = (int32_t)h[4];
+    const uint32_t np = h[5];
+    if (h[0] != kRleMagic || w < 0 || hh < 0 || (np != 4 && np != 8) || h[6] != (uint32_t)kBlock)
       err = CMP_ECORRUPT;
-    } else {
-      const u32x4 h0 = reinterpret_cast<const u32x4*>(I.in)[0];
-      const u32x4 h1 = reinterpret_cast<const u32x4*>(I.in)[1];
-      h[0] = h0.x; h[1] = h0.y; h[2] = h0.z; h[3] = h0.w;
-      h[4] = h1.x; h[5] = h1.y; h[6] = h1.z; h[7] = h1.w;
-      const int32_t w = (int32_t)h[3], hh = (int32_t)h[4];
-      const uint32_t np = h[5];
-      if (h[0] != kRleMagic || w < 0 || hh < 0 || (np != 4 && np != 8) || h[6] != (uint32_t)kBlock)
-        err = CMP_ECORRUPT;
-      else if ((uint64_t)h[7] != rle_nblocks((int64_t)w * hh))
-        err = CMP_ECORRUPT;
-      else if (I.in_bytes < rle_p0(h[7], (int)np))
-        err = CMP_ECORRUPT;
-      else if (w > I.cap_w || hh > I.cap_h || (np == 8 && !I.depth))
-        err = CMP_ENOSPC;
-    }
-    uint32_t boff = 0;
-    if (!err && (uint32_t)b < h[7]) {
-      const uint64_t nb = h[7];
-      const int np = (int)h[5];
-      const int64_t npx = (int64_t)(int32_t)h[3] * (int32_t)h[4];
-      const uint32_t len = (uint32_t)imin64(kBlock, npx - (int64_t)b * kBlock);
-      const uint32_t* tbl = reinterpret_cast<const uint32_t*>(I.in + 32);
-      boff = tbl[b];
-      uint64_t tot = 0;
-      for (int k = 0; k < np; ++k) {
-        const uint32_t sz = tbl[nb + (uint64_t)b * np + k];
-        s_size[k] = sz;
-        if (sz > len || (sz < len && (sz == 0 || (sz & 1u)))) err = CMP_ECORRUPT;
-        tot += sz;
-      }
-      const uint64_t P0 = rle_p0(nb, np);
-      if ((boff & 15u) || (b == 0 && boff != 0)) err = CMP_ECORRUPT;
-      if ((uint64_t)b + 1 < nb && (uint64_t)tbl[b + 1] != boff + align16(tot)) err = CMP_ECORRUPT;
-      if (P0 + boff + align16(tot) > I.in_bytes) err = CMP_ECORRUPT;
-    }
-    if (err && (b == 0 || err == CMP_ECORRUPT)) a.status[s] = err;
-    for (int k = 0; k < 8; ++k) s_hdr[k] = h[k];
-    s_boff = boff;
-    s_err = err;
+    else if ((uint64_t)h[7] != rle_nblocks((int64_t)w * hh))
+      err = CMP_ECORRUPT;
+    else if (I.in_bytes < rle_p0(h[7], (int)np))
+      err = CMP_ECORRUPT;
+    else if (w > I.cap_w || hh > I.cap_h || (np == 8 && !I.depth))
+      err = CMP_ENOSPC;
   }
-  __syncthreads();
-  if (s_err) return;
-  const int32_t rw = (int32_t)s_hdr[3], rh = (int32_t)s_hdr[4];
-  const int np = (int)s_hdr[5];
-  const uint64_t nb = s_hdr[7];
-  if (b == 0 && a.roi_out && tid < 4)
-    a.roi_out[4 * s + tid] = (int32_t)(tid == 0 ? s_hdr[1] : tid == 1 ? s_hdr[2] : s_hdr[3 + tid - 2]);
+  if (err) {
+    if (tid == 0 && (b == 0 || err == CMP_ECORRUPT)) a.status[s] = err;
+    return;
+  }
+  const int32_t rw = (int32_t)h[3], rh = (int32_t)h[4];
+  const int np = (int)h[5];
+  const uint64_t nb = h[7];
+  if (b == 0 && a.roi_out && tid == 0)
+    reinterpret_cast<int4*>(a.roi_out)[s] = int4{(int)h[1], (int)h[2], (int)h[3], (int)h[4]};
   if ((uint64_t)b >= nb) return;
   const int64_t npx = (int64_t)rw * rh;
   const int len = (int)imin64(kBlock, npx - (int64_t)b * kBlock);
+  const uint32_t* tbl = reinterpret_cast<const uint32_t*>(I.in + 32);
+  if (tid < np) s_size[tid] = tbl[nb + (uint64_t)b * np + tid];
+  if (tid == 8) s_boff = tbl[b];
+  if (tid == 9) s_next = (uint64_t)b + 1 < nb ? tbl[b + 1] : 0u;
+  __syncthreads();
+  if (tid == 0) {
+    int e = 0;
+    uint64_t tot = 0;
+    for (int k = 0; k < np; ++k) {
+      const uint32_t sz = s_size[k];
+      if (sz > (uint32_t)len || (sz < (uint32_t)len && (sz == 0 || (sz & 1u)))) e = CMP_ECORRUPT;
+      tot += sz;
+    }
+    const uint32_t boff = s_boff;
+    if ((boff & 15u) || (b == 0 && boff != 0)) e = CMP_ECORRUPT;
+    if ((uint64_t)b + 1 < nb && (uint64_t)s_next != boff + align16(tot)) e = CMP_ECORRUPT;
+    if (rle_p0(nb, np) + boff + align16(tot) > I.in_bytes) e = CMP_ECORRUPT;
+    if (e) a.status[s] = e;
+    s_err = e;
+  }
+  __syncthreads();
+  if (s_err) return;
   uint32_t size[8], poff[8], total = 0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -479,9 +492,19 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
   }
   const uint32_t padded = (uint32_t)align16(total);
   {
+    // the whole block payload to LDS: all loads in flight before the stores
     const u32x4* src = reinterpret_cast<const u32x4*>(I.in + rle_p0(nb, np) + s_boff);
     u32x4* dst = reinterpret_cast<u32x4*>(stage);
-    for (uint32_t i = tid; i < padded / 16; i += kThreads) dst[i] = src[i];
+    const uint32_t nv = padded / 16;
+    constexpr int kMaxPer = (8 * kBlock / 16 + kThreads - 1) / kThreads;
+    u32x4 tmp[kMaxPer];
+    const int nvi = (int)nv;
+#pragma unroll
+    for (int k = 0; k < kMaxPer; ++k)
+      tmp[k] = tid + k * kThreads < nvi ? __builtin_nontemporal_load(&src[tid + k * kThreads]) : u32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < kMaxPer; ++k)
+      if (tid + k * kThreads < nvi) dst[tid + k * kThreads] = tmp[k];
   }
   __syncthreads();
 
@@ -490,64 +513,68 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
 #pragma unroll
   for (int j = 0; j < kPxPerLane; ++j) { col[j] = 0; dep[j] = 0; }
   bool bad = false;
+#pragma unroll 1
   for (int k = 0; k < np; ++k) {
     const uint32_t off = poff[k];
     const int sh8 = 8 * (k & 3);
+    u32x4 pb;   // this lane's 16 bytes of plane k
     if (size[k] == (uint32_t)len) {
+      uint32_t w4[4] = {0, 0, 0, 0};
 #pragma unroll
-      for (int j = 0; j < kPxPerLane; ++j) {
-        if (q0 + j < len) {
-          const uint32_t v = stage[off + q0 + j];
-          if (k < 4) col[j] |= v << sh8; else dep[j] |= v << sh8;
+      for (int j = 0; j < kPxPerLane; ++j)
+        if (q0 + j < len) w4[j >> 2] |= (uint32_t)stage[off + q0 + j] << (8 * (j & 3));
+      pb = u32x4{w4[0], w4[1], w4[2], w4[3]};
+    } else {
+      // run lengths -> inclusive ends (8 tokens per lane)
+      const int ntok = (int)(size[k] / 2);
+      uint32_t lens[8];
+      uint32_t mysum = 0;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int ti = tid * 8 + t;
+        lens[t] = ti < ntok ? (uint32_t)stage[off + 2 * ti] + 1u : 0u;
+        mysum += lens[t];
+      }
+      uint64_t ex, ex2, tot, tot2;
+      block_scan2(mysum, 0, ex, ex2, tot, tot2, sh);
+      uint32_t run = (uint32_t)ex;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int ti = tid * 8 + t;
+        run += lens[t];
+        if (ti < ntok) ends[ti] = (uint16_t)min(run, 65535u);
+      }
+      if ((uint32_t)tot != (uint32_t)len) bad = true;   // uniform
+      __syncthreads();
+      if (!bad && q0 < len) {
+        // first run that ends after q0, then walk the runs over the lane's bytes
+        int lo = 0, hi = ntok - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if ((int)ends[mid] > q0) hi = mid; else lo = mid + 1;
         }
-      }
-      continue;
-    }
-    // run lengths -> inclusive ends (8 tokens per lane)
-    const int ntok = (int)(size[k] / 2);
-    uint32_t lens[8];
-    uint32_t mysum = 0;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int ti = tid * 8 + t;
-      lens[t] = ti < ntok ? (uint32_t)stage[off + 2 * ti] + 1u : 0u;
-      mysum += lens[t];
-    }
-    uint64_t ex, ex2, tot, tot2;
-    block_scan2(mysum, 0, ex, ex2, tot, tot2, sh);
-    uint32_t run = (uint32_t)ex;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int ti = tid * 8 + t;
-      run += lens[t];
-      if (ti < ntok) ends[ti] = (uint16_t)min(run, 65535u);
-    }
-    if ((uint32_t)tot != (uint32_t)len) bad = true;   // uniform
-    __syncthreads();
-    if (!bad && q0 < len) {
-      // first run that ends after q0
-      int lo = 0, hi = ntok - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((int)ends[mid] > q0) hi = mid; else lo = mid + 1;
-      }
-      int tok = lo;
-      int e = ends[tok];
-      uint32_t v = stage[off + 2 * tok + 1];
-#pragma unroll
-      for (int j = 0; j < kPxPerLane; ++j) {
-        const int pos = q0 + j;
-        if (pos < len) {
+        int tok = lo;
+        int e = ends[tok];
+        uint8_t v = stage[off + 2 * tok + 1];
+        const int last = min(q0 + kPxPerLane, len);
+        for (int pos = q0; pos < last; ++pos) {
           while (pos >= e && tok + 1 < ntok) {
             ++tok;
             e = ends[tok];
             v = stage[off + 2 * tok + 1];
           }
-          if (k < 4) col[j] |= v << sh8; else dep[j] |= v << sh8;
+          plane_buf[pos] = v;
         }
       }
+      pb = reinterpret_cast<const u32x4*>(plane_buf)[tid];   // own bytes only: no barrier
+      __syncthreads();   // ends[] is rewritten by the next plane
     }
-    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPxPerLane; ++j) {
+      const uint32_t wv = (j < 4 ? pb.x : j < 8 ? pb.y : j < 12 ? pb.z : pb.w);
+      const uint32_t v = (wv >> (8 * (j & 3))) & 0xFFu;
+      if (k < 4) col[j] |= v << sh8; else dep[j] |= v << sh8;
+    }
   }
   if (bad) {
     if (tid == 0) a.status[s] = CMP_ECORRUPT;

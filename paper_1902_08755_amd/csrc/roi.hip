@@ -15,6 +15,7 @@
 namespace cmp {
 
 constexpr int kRoiMax = 64;
+constexpr int kRoiBatch = 8;
 
 struct RoiImg {
   const void* color;
@@ -91,25 +92,39 @@ __global__ __launch_bounds__(kThreads) void roi_kernel(const RoiArgs a) {
   int minx = 0x7FFFFFFF, miny = 0x7FFFFFFF, maxx = -1, maxy = -1;
   const int per_row = full_units + tail;
   const int work = per_row * (y1 - y0);
-  for (int t = threadIdx.x; t < work; t += kThreads) {
-    const int ry = t / per_row;
-    const int u = t - ry * per_row;
-    const int y = y0 + ry;
-    const uint8_t* row = base + (int64_t)y * row_bytes;
-    uint32_t m;
-    int x;
-    if (u < full_units) {
-      m = unit_mask<MODE>(reinterpret_cast<const u32x4*>(row)[u]);
-      x = u * ppu;
-    } else {
-      x = full_units * ppu + (u - full_units);
-      m = px_mask<MODE>(row, x);
+  // lane t takes units t, t + 256, ...; (row, unit) advance incrementally and
+  // kRoiBatch loads are issued before any of them is examined
+  int ry = per_row ? threadIdx.x / per_row : 0;
+  int u = threadIdx.x - ry * per_row;
+  for (int t0 = threadIdx.x; t0 < work; t0 += kThreads * kRoiBatch) {
+    uint32_t m[kRoiBatch];
+    int xs[kRoiBatch], ys[kRoiBatch];
+#pragma unroll
+    for (int k = 0; k < kRoiBatch; ++k) {
+      m[k] = 0;
+      xs[k] = 0;
+      ys[k] = y0 + ry;
+      if (t0 + k * kThreads < work) {
+        const uint8_t* row = base + (int64_t)(y0 + ry) * row_bytes;
+        if (u < full_units) {
+          m[k] = unit_mask<MODE>(reinterpret_cast<const u32x4*>(row)[u]);
+          xs[k] = u * ppu;
+        } else {
+          xs[k] = full_units * ppu + (u - full_units);
+          m[k] = px_mask<MODE>(row, xs[k]);
+        }
+      }
+      u += kThreads;
+      while (u >= per_row && per_row > 0) { u -= per_row; ++ry; }
     }
-    if (m) {
-      minx = min(minx, x + (int)__builtin_ctz(m));
-      maxx = max(maxx, x + 31 - (int)__builtin_clz(m));
-      miny = min(miny, y);
-      maxy = max(maxy, y);
+#pragma unroll
+    for (int k = 0; k < kRoiBatch; ++k) {
+      if (m[k]) {
+        minx = min(minx, xs[k] + (int)__builtin_ctz(m[k]));
+        maxx = max(maxx, xs[k] + 31 - (int)__builtin_clz(m[k]));
+        miny = min(miny, ys[k]);
+        maxy = max(maxy, ys[k]);
+      }
     }
   }
   __shared__ int4 red[kThreads / kWave];
@@ -170,10 +185,10 @@ __global__ __launch_bounds__(kThreads) void roi_kernel(const RoiArgs a) {
   }
 }
 
-// Rows per workgroup: about 64 KiB of reads per workgroup.
+// Rows per workgroup: about 128 KiB of reads per workgroup.
 static int roi_rows(const cmp_image& I, int bpp) {
   const int64_t row_bytes = (int64_t)(I.roi.w > 0 ? I.roi.w : 1) * bpp;
-  int64_t r = (64 * 1024 + row_bytes - 1) / row_bytes;
+  int64_t r = (128 * 1024 + row_bytes - 1) / row_bytes;
   if (r < 1) r = 1;
   if (r > I.roi.h) r = I.roi.h > 0 ? I.roi.h : 1;
   return (int)r;
