@@ -75,7 +75,7 @@ class Frame:
                                   self.roi_ws.data_ptr(), self.roi_ws.numel(), s)
         elif k == 1:
             r = self.rle
-            st = L.cmp_rle_compress(r.arr, 16, cmp.RGBA8, self.roi.data_ptr(), r.out_ptrs,
+            st = L.cmp_rle_compress(r.arr, 16, cmp.RGBA8, 0, self.roi.data_ptr(), r.out_ptrs,
                                     r.cap_arr, r.sizes.data_ptr(), r.status.data_ptr(),
                                     r.ws.data_ptr(), r.ws.numel(), s)
         elif k == 2:

@@ -196,8 +196,8 @@ cmp_status cmp_roi_detect(const cmp_image* imgs, int32_t n, cmp_format fmt, int3
  * one RLE stream per component of the pixel, and the image decomposed into
  * sub-images that are compressed in parallel). Stream format "RLE1"; all
  * integers little-endian uint32:
- *   header  magic 0x31454C52, roi.x, roi.y, roi.w, roi.h, nplanes, 4096,
- *           nblocks = ceil(roi.w roi.h / 4096)
+ *   header  magic 0x31454C52, roi.x, roi.y, roi.w, roi.h, nplanes (| 0x100
+ *           when the colour is bit-swizzled), 4096, nblocks = ceil(w h / 4096)
  *   boff[nblocks]           payload offset of block b (multiple of 16)
  *   size[nblocks][nplanes]  encoded bytes of (block b, plane k)
  *   zero bytes to a multiple of 16; then the payload: per block, its planes'
@@ -212,9 +212,17 @@ cmp_status cmp_roi_detect(const cmp_image* imgs, int32_t n, cmp_format fmt, int3
  */
 size_t cmp_rle_max_size(int32_t w, int32_t h, int32_t nplanes);
 
+/* Bit swizzling of the colour words before their planes are taken (Section
+ * 5.5.1: a preconditioner that groups the colour bits by significance). The
+ * bit pattern is this library's: byte j of the swizzled word holds bits
+ * 2j+1 and 2j of R, G, B and A (component c at bits 8j + 2c .. 8j + 2c + 1).
+ * The stream records it as 0x100 in header word 5 (next to nplanes);
+ * decompression undoes it. */
+#define CMP_RLE_SWIZZLE 1u
+
 /*
  * Compress n images (fmt CMP_RGBA8; 8 planes when imgs[i].depth != NULL,
- * else 4) in one launch.
+ * else 4) in one launch. flags: 0 or CMP_RLE_SWIZZLE.
  *   imgs[i]       image of imgs[i].roi.w x imgs[i].roi.h pixels (x/y ignored).
  *   roi_dev       NULL (whole images) or device int32[n][4] image-local ROIs,
  *                 e.g. the output of cmp_roi_detect; clamped to the image.
@@ -230,7 +238,7 @@ size_t cmp_rle_max_size(int32_t w, int32_t h, int32_t nplanes);
  * n <= 64. Errors: CMP_EINVAL, CMP_ENOSPC, CMP_EUNSUPPORTED, CMP_EHIP.
  */
 size_t     cmp_rle_workspace_size(const cmp_image* imgs, int32_t n);
-cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_format fmt,
+cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_format fmt, uint32_t flags,
                             const int32_t* roi_dev, uint8_t* const* out,
                             const uint64_t* capacity, uint64_t* out_size_dev,
                             int32_t* status_dev, void* workspace, size_t ws_bytes,

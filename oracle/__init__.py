@@ -74,10 +74,14 @@ def lib():
             getattr(L, name).restype = Rect
         L.orc_rle_max_size.argtypes = [i32, i32, i32]
         L.orc_rle_max_size.restype = u64
-        L.orc_rle_compress.argtypes = [P, P, i64, Rect, P, u64]
+        L.orc_rle_compress.argtypes = [P, P, i64, Rect, i32, P, u64]
         L.orc_rle_compress.restype = u64
         L.orc_rle_header.argtypes = [P, u64, ctypes.POINTER(Rect), ctypes.POINTER(i32),
-                                     ctypes.POINTER(u64)]
+                                     ctypes.POINTER(i32), ctypes.POINTER(u64)]
+        L.orc_swizzle.argtypes = [ctypes.c_uint32]
+        L.orc_swizzle.restype = ctypes.c_uint32
+        L.orc_unswizzle.argtypes = [ctypes.c_uint32]
+        L.orc_unswizzle.restype = ctypes.c_uint32
         L.orc_rle_header.restype = ctypes.c_int
         L.orc_rle_decompress.argtypes = [P, u64, P, P, i64, ctypes.POINTER(Rect)]
         L.orc_rle_decompress.restype = ctypes.c_int
@@ -234,10 +238,20 @@ def rle_max_size(w, h, nplanes):
     return int(lib().orc_rle_max_size(w, h, nplanes))
 
 
-def rle_compress(color, depth, roi):
+def swizzle(word: int) -> int:
+    """The bit-swizzling preconditioner of Section 5.5.1 on one RGBA8 word."""
+    return int(lib().orc_swizzle(word))
+
+
+def unswizzle(word: int) -> int:
+    return int(lib().orc_unswizzle(word))
+
+
+def rle_compress(color, depth, roi, swizzle=False):
     """Per-component RLE of the ROI of an RGBA8 (+ depth) image (Section 5.5.1).
 
     color/depth: uint32 (H, pitch) full images; roi: image-local (x, y, w, h).
+    swizzle: bit-swizzle the colour words first (Section 5.5.1).
     Returns the RLE1 stream as a uint8 array.
     """
     c = _contig(color, np.uint32)
@@ -250,7 +264,7 @@ def rle_compress(color, depth, roi):
     cap = rle_max_size(w, h, nplanes)
     out = np.zeros(cap, np.uint8)
     sz = lib().orc_rle_compress(_ptr(c), None if d is None else _ptr(d), c.shape[1],
-                                Rect(*roi), _ptr(out), cap)
+                                Rect(*roi), int(bool(swizzle)), _ptr(out), cap)
     if sz == 0:
         raise ValueError("rle_compress failed")
     return out[:sz].copy()
@@ -258,9 +272,9 @@ def rle_compress(color, depth, roi):
 
 def rle_header(stream):
     s = np.ascontiguousarray(np.asarray(stream, dtype=np.uint8))
-    r, npl, tot = Rect(), ctypes.c_int32(), ctypes.c_uint64()
+    r, npl, swz, tot = Rect(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_uint64()
     rc = lib().orc_rle_header(_ptr(s), s.size, ctypes.byref(r), ctypes.byref(npl),
-                              ctypes.byref(tot))
+                              ctypes.byref(swz), ctypes.byref(tot))
     if rc != 0:
         return None
     return r.tup(), npl.value, tot.value

@@ -386,19 +386,52 @@ uint64_t orc_rle_max_size(int32_t w, int32_t h, int32_t nplanes)
     return total;
 }
 
+/* Bit swizzling (Section 5.5.1: a preconditioner that regroups the colour */
+/* bits by significance, so that per-component RLE compresses the high,     */
+/* middle and low bits of all four components in separate streams). The    */
+/* bit pattern is this library's own: byte j of the swizzled word holds     */
+/* bits 2j+1 and 2j of R, G, B and A, in that order from its low end, i.e.  */
+/* bit 2j+b of component c moves to bit 8j + 2c + b.                        */
+uint32_t orc_swizzle(uint32_t rgba)
+{
+    uint32_t out = 0;
+    for (int c = 0; c < 4; ++c)
+        for (int j = 0; j < 4; ++j)
+            for (int b = 0; b < 2; ++b) {
+                const uint32_t bit = (rgba >> (8 * c + 2 * j + b)) & 1u;
+                out |= bit << (8 * j + 2 * c + b);
+            }
+    return out;
+}
+
+uint32_t orc_unswizzle(uint32_t s)
+{
+    uint32_t out = 0;
+    for (int c = 0; c < 4; ++c)
+        for (int j = 0; j < 4; ++j)
+            for (int b = 0; b < 2; ++b) {
+                const uint32_t bit = (s >> (8 * j + 2 * c + b)) & 1u;
+                out |= bit << (8 * c + 2 * j + b);
+            }
+    return out;
+}
+
 /* byte k of pixel q of the ROI (q row-major over the ROI) */
 static uint8_t plane_byte(const uint32_t* color, const uint32_t* depth, int64_t pitch,
-                          orc_rect roi, int64_t q, int k)
+                          orc_rect roi, int64_t q, int k, int swizzle)
 {
     const int64_t yy = q / roi.w, xx = q % roi.w;
     const int64_t off = (roi.y + yy) * pitch + (roi.x + xx);
-    const uint32_t word = k < 4 ? color[off] : depth[off];
+    uint32_t word = k < 4 ? color[off] : depth[off];
+    if (k < 4 && swizzle) word = orc_swizzle(word);
     return (uint8_t)(word >> (8 * (k & 3)));
 }
 
 /* Returns the stream size, or 0 if `cap` is too small or the ROI invalid. */
+/* With `swizzle`, the colour words are bit-swizzled before their planes    */
+/* are taken, and header word 5 carries the flag 0x100 next to nplanes.     */
 uint64_t orc_rle_compress(const uint32_t* color, const uint32_t* depth, int64_t pitch,
-                          orc_rect roi, uint8_t* out, uint64_t cap)
+                          orc_rect roi, int32_t swizzle, uint8_t* out, uint64_t cap)
 {
     const int32_t nplanes = depth ? 8 : 4;
     if (roi.w < 0 || roi.h < 0) return 0;
@@ -411,7 +444,8 @@ uint64_t orc_rle_compress(const uint32_t* color, const uint32_t* depth, int64_t 
     put32(out + 0, RLE_MAGIC);
     put32(out + 4, (uint32_t)roi.x); put32(out + 8, (uint32_t)roi.y);
     put32(out + 12, (uint32_t)roi.w); put32(out + 16, (uint32_t)roi.h);
-    put32(out + 20, (uint32_t)nplanes); put32(out + 24, RLE_BLOCK); put32(out + 28, (uint32_t)nb);
+    put32(out + 20, (uint32_t)nplanes | (swizzle ? 0x100u : 0u));
+    put32(out + 24, RLE_BLOCK); put32(out + 28, (uint32_t)nb);
     uint8_t* boff = out + 32;
     uint8_t* sizes = out + 32 + 4 * nb;
     uint64_t pos = 0; /* payload-relative */
@@ -422,7 +456,8 @@ uint64_t orc_rle_compress(const uint32_t* color, const uint32_t* depth, int64_t 
         put32(boff + 4 * b, (uint32_t)pos);
         uint64_t block_bytes = 0;
         for (int k = 0; k < nplanes; ++k) {
-            for (int64_t j = 0; j < len; ++j) plane[j] = plane_byte(color, depth, pitch, roi, q0 + j, k);
+            for (int64_t j = 0; j < len; ++j)
+                plane[j] = plane_byte(color, depth, pitch, roi, q0 + j, k, swizzle);
             /* count maximal runs that stay inside a 256-pixel segment */
             int64_t ntok = 0;
             for (int64_t j = 0; j < len;) {
@@ -459,14 +494,17 @@ uint64_t orc_rle_compress(const uint32_t* color, const uint32_t* depth, int64_t 
 }
 
 /* Parses the header. Returns 0 and fills the outputs, or -1 if corrupt. */
-int orc_rle_header(const uint8_t* in, uint64_t size, orc_rect* roi, int32_t* nplanes, uint64_t* total)
+int orc_rle_header(const uint8_t* in, uint64_t size, orc_rect* roi, int32_t* nplanes,
+                   int32_t* swizzle, uint64_t* total)
 {
     if (size < 32) return -1;
     if (get32(in) != RLE_MAGIC) return -1;
     orc_rect r;
     r.x = (int32_t)get32(in + 4); r.y = (int32_t)get32(in + 8);
     r.w = (int32_t)get32(in + 12); r.h = (int32_t)get32(in + 16);
-    const uint32_t np = get32(in + 20);
+    const uint32_t w5 = get32(in + 20);
+    const uint32_t np = w5 & 0xFFu;
+    if (w5 & ~0x1FFu) return -1;
     if (r.w < 0 || r.h < 0) return -1;
     if (np != 4 && np != 8) return -1;
     if (get32(in + 24) != RLE_BLOCK) return -1;
@@ -489,7 +527,7 @@ int orc_rle_header(const uint8_t* in, uint64_t size, orc_rect* roi, int32_t* npl
         pos += align16(block_bytes);
     }
     if (size < P0 + pos) return -1;
-    *roi = r; *nplanes = (int32_t)np; *total = P0 + pos;
+    *roi = r; *nplanes = (int32_t)np; *swizzle = (w5 >> 8) & 1; *total = P0 + pos;
     return 0;
 }
 
@@ -500,8 +538,8 @@ int orc_rle_header(const uint8_t* in, uint64_t size, orc_rect* roi, int32_t* npl
 int orc_rle_decompress(const uint8_t* in, uint64_t size, uint32_t* out_color, uint32_t* out_depth,
                        int64_t out_pitch, orc_rect* roi_out)
 {
-    orc_rect r; int32_t np; uint64_t total;
-    if (orc_rle_header(in, size, &r, &np, &total) != 0) return -1;
+    orc_rect r; int32_t np, swz; uint64_t total;
+    if (orc_rle_header(in, size, &r, &np, &swz, &total) != 0) return -1;
     if (np == 8 && !out_depth) return -1;
     const int64_t npx = (int64_t)r.w * r.h;
     const uint64_t nb = rle_nblocks(npx);
@@ -535,6 +573,10 @@ int orc_rle_decompress(const uint8_t* in, uint64_t size, uint32_t* out_color, ui
             }
         }
     }
+    if (swz)
+        for (int64_t yy = 0; yy < r.h; ++yy)
+            for (int64_t xx = 0; xx < r.w; ++xx)
+                out_color[yy * out_pitch + xx] = orc_unswizzle(out_color[yy * out_pitch + xx]);
     if (roi_out) *roi_out = r;
     return 0;
 }

@@ -27,6 +27,7 @@ LIB_PATH = os.path.join(_HERE, "libcmp.so")
 CMP_OK, CMP_EINVAL, CMP_ENOSPC, CMP_EHIP, CMP_EUNSUPPORTED, CMP_ECORRUPT, CMP_ETIMEOUT = (
     0, -1, -2, -3, -4, -5, -6)
 RGBA8, RGBA32F, RGBA16F = 0, 1, 2
+RLE_SWIZZLE = 1
 SEQ, DIRECT_SEND, BINARY_SWAP = 0, 1, 2
 _SCHED = {"seq": SEQ, "direct_send": DIRECT_SEND, "binary_swap": BINARY_SWAP}
 
@@ -88,7 +89,7 @@ def lib() -> ctypes.CDLL:
         "cmp_roi_detect": ([IMG, i32, i32, P, P, sz, P], i32),
         "cmp_rle_max_size": ([i32, i32, i32], sz),
         "cmp_rle_workspace_size": ([IMG, i32], sz),
-        "cmp_rle_compress": ([IMG, i32, i32, P, P, P, P, P, P, sz, P], i32),
+        "cmp_rle_compress": ([IMG, i32, i32, ctypes.c_uint32, P, P, P, P, P, P, sz, P], i32),
         "cmp_rle_decompress": ([P, P, i32, IMG, P, P, P], i32),
         "cmp_batch_plan_create": ([ctypes.POINTER(CJob), i32, ctypes.c_char_p,
                                    ctypes.POINTER(P)], i32),
@@ -309,7 +310,8 @@ def rle_max_size(w: int, h: int, nplanes: int) -> int:
 class RleBatch:
     """Pre-marshalled arguments of one cmp_rle_compress call over n images."""
 
-    def __init__(self, images: Sequence, roi_dev=None, outs=None):
+    def __init__(self, images: Sequence, roi_dev=None, outs=None, swizzle=False):
+        self.flags = RLE_SWIZZLE if swizzle else 0
         self.images = list(images)
         n = self.n = len(images)
         self.arr = _images(images, "u32")
@@ -326,7 +328,7 @@ class RleBatch:
         self.ws = torch.zeros(max(need, 256), dtype=torch.uint8, device=dev)
 
     def run(self, stream=None):
-        st = lib().cmp_rle_compress(self.arr, self.n, RGBA8, _cuda(self.roi_dev, "roi_dev"),
+        st = lib().cmp_rle_compress(self.arr, self.n, RGBA8, self.flags, _cuda(self.roi_dev, "roi_dev"),
                                     self.out_ptrs, self.cap_arr, self.sizes.data_ptr(),
                                     self.status.data_ptr(), self.ws.data_ptr(), self.ws.numel(),
                                     _stream(stream))
@@ -334,10 +336,10 @@ class RleBatch:
         return self.outs, self.sizes
 
 
-def rle_compress(images: Sequence, roi_dev=None, stream=None):
+def rle_compress(images: Sequence, roi_dev=None, swizzle=False, stream=None):
     """Per-component RLE of n images (cmp_rle_compress). Returns (streams,
     sizes): full-capacity uint8 buffers and an int64 tensor of stream sizes."""
-    return RleBatch(images, roi_dev).run(stream)
+    return RleBatch(images, roi_dev, swizzle=swizzle).run(stream)
 
 
 def rle_decompress(streams: Sequence[torch.Tensor], outs: Sequence, stream=None, roi_out=None,

@@ -23,7 +23,26 @@ struct OverDesc {
   int32_t x, y, w, h;  // placement
 };
 
-constexpr int kOverBatch = 8;
+// A stored pixel before widening: FP16 pixels stay packed in two registers
+// until they are blended.
+template <int FMT>
+struct RawPx { typedef f32x4 type; };
+template <>
+struct RawPx<CMP_RGBA16F> { typedef f16x4 type; };
+
+template <int FMT>
+__device__ __forceinline__ typename RawPx<FMT>::type ld_raw(const void* base, int64_t px) {
+  return reinterpret_cast<const typename RawPx<FMT>::type*>(base)[px];
+}
+__device__ __forceinline__ f32x4 widen(f32x4 v) { return v; }
+__device__ __forceinline__ f32x4 widen(f16x4 h) {
+  return f32x4{(float)h.x, (float)h.y, (float)h.z, (float)h.w};
+}
+
+// Layers whose loads are in flight together: 128 bytes per lane either way.
+template <int FMT>
+constexpr int over_batch() { return FMT == CMP_RGBA32F ? 8 : 16; }
+constexpr int kOverBatch = 8;   // the backward pass (FP32 and FP16 alike)
 
 __device__ __forceinline__ f32x4 over_op(f32x4 front, f32x4 back) {
   const float t = 1.0f - front.w;
@@ -42,12 +61,14 @@ template <int FMT>
 __device__ __forceinline__ f32x4 over_range(const OverDesc* __restrict__ d, int j0, int j1,
                                             int X, int Y, int x0, int y0, int tw, int th,
                                             f32x4 acc) {
-  for (int jb = j0; jb < j1; jb += kOverBatch) {
-    f32x4 L[kOverBatch];
-    bool cov[kOverBatch];
+  constexpr int B = over_batch<FMT>();
+  typedef typename RawPx<FMT>::type Raw;
+  for (int jb = j0; jb < j1; jb += B) {
+    Raw L[B];
+    bool cov[B];
 #pragma unroll
-    for (int k = 0; k < kOverBatch; ++k) {
-      L[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < B; ++k) {
+      L[k] = Raw{0, 0, 0, 0};
       cov[k] = false;
       const int j = jb + k;
       if (j >= j1) continue;
@@ -55,11 +76,11 @@ __device__ __forceinline__ f32x4 over_range(const OverDesc* __restrict__ d, int 
       if (tile_misses(D.x, D.y, D.w, D.h, x0, y0, tw, th)) continue;
       if (X < D.x || X >= D.x + D.w || Y < D.y || Y >= D.y + D.h) continue;
       cov[k] = true;
-      L[k] = ld_rgba<FMT>(D.color, (int64_t)(Y - D.y) * D.pitch + (X - D.x));
+      L[k] = ld_raw<FMT>(D.color, (int64_t)(Y - D.y) * D.pitch + (X - D.x));
     }
 #pragma unroll
-    for (int k = 0; k < kOverBatch; ++k)
-      if (cov[k]) acc = over_op(L[k], acc);
+    for (int k = 0; k < B; ++k)
+      if (cov[k]) acc = over_op(widen(L[k]), acc);
   }
   return acc;
 }

@@ -95,6 +95,19 @@ __device__ __forceinline__ uint32_t field16(uint64_t lo, uint64_t hi, int k) {
 
 __device__ __forceinline__ uint32_t byte_of(uint32_t w, int k) { return (w >> (8 * (k & 3))) & 0xFFu; }
 
+// Bit swizzling (Section 5.5.1): bit 2j+b of component c moves to bit
+// 8j + 2c + b, i.e. the 4x4 matrix of 2-bit fields (component, significance
+// group) is transposed. Two delta swaps do the transpose: the off-diagonal
+// 2x2 blocks, then the off-diagonal fields inside each block. A transpose is
+// its own inverse, so the same function undoes it.
+__device__ __forceinline__ uint32_t swizzle_bits(uint32_t x) {
+  uint32_t t = ((x >> 12) ^ x) & 0x0000F0F0u;
+  x ^= t ^ (t << 12);
+  t = ((x >> 6) ^ x) & 0x00CC00CCu;
+  x ^= t ^ (t << 6);
+  return x;
+}
+
 // Clamp a device ROI to a W x H image.
 __device__ __forceinline__ void clamp_roi(const int32_t* roi_dev, int s, int W, int H, int& x,
                                           int& y, int& w, int& h) {
@@ -130,6 +143,7 @@ struct RleCArgs {
   uint32_t* ctl;           // workspace: [0] ticket, [1] done, [2] epoch
   uint64_t* flags;         // workspace: one flag per (image, block)
   int32_t n;
+  int32_t swizzle;         // CMP_RLE_SWIZZLE
 };
 static_assert(sizeof(RleCArgs) <= 4096, "kernel arguments must fit in 4 KiB");
 
@@ -178,8 +192,8 @@ __global__ __launch_bounds__(kThreads) void rle_compress_kernel(const RleCArgs a
     uint8_t* out = I.out;
     if (nb == 0) {
       if (tid < 8) {
-        const uint32_t hdr[8] = {kRleMagic, (uint32_t)rx, (uint32_t)ry, 0u, 0u, (uint32_t)np,
-                                 (uint32_t)kBlock, 0u};
+        const uint32_t hdr[8] = {kRleMagic, (uint32_t)rx, (uint32_t)ry, 0u, 0u,
+                                 (uint32_t)np | (a.swizzle ? 0x100u : 0u), (uint32_t)kBlock, 0u};
         reinterpret_cast<uint32_t*>(out)[tid] = hdr[tid];
       }
       if (tid == 0) a.out_size[s] = 32;
@@ -218,6 +232,10 @@ __global__ __launch_bounds__(kThreads) void rle_compress_kernel(const RleCArgs a
             }
           }
         }
+      }
+      if (a.swizzle) {
+#pragma unroll
+        for (int j = 0; j < kPxPerLane; ++j) col[j] = swizzle_bits(col[j]);
       }
       const uint32_t pcol = __shfl_up(col[kPxPerLane - 1], 1);
       const uint32_t pdep = __shfl_up(dep[kPxPerLane - 1], 1);
@@ -367,7 +385,8 @@ __global__ __launch_bounds__(kThreads) void rle_compress_kernel(const RleCArgs a
       if (b == 0) {
         if (tid < 8) {
           const uint32_t hdr[8] = {kRleMagic, (uint32_t)rx, (uint32_t)ry, (uint32_t)rw,
-                                   (uint32_t)rh, (uint32_t)np, (uint32_t)kBlock, (uint32_t)nb};
+                                   (uint32_t)rh, (uint32_t)np | (a.swizzle ? 0x100u : 0u),
+                                   (uint32_t)kBlock, (uint32_t)nb};
           reinterpret_cast<uint32_t*>(out)[tid] = hdr[tid];
         }
         const uint64_t tend = 32 + 4 * nb * (1 + (uint64_t)np);
@@ -439,8 +458,9 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
     h[0] = h0.x; h[1] = h0.y; h[2] = h0.z; h[3] = h0.w;
     h[4] = h1.x; h[5] = h1.y; h[6] = h1.z; h[7] = h1.w;
     const int32_t w = (int32_t)h[3], hh = (int32_t)h[4];
-    const uint32_t np = h[5];
-    if (h[0] != kRleMagic || w < 0 || hh < 0 || (np != 4 && np != 8) || h[6] != (uint32_t)kBlock)
+    const uint32_t np = h[5] & 0xFFu;
+    if (h[0] != kRleMagic || w < 0 || hh < 0 || (np != 4 && np != 8) || h[6] != (uint32_t)kBlock ||
+        (h[5] & ~0x1FFu))
       err = CMP_ECORRUPT;
     else if ((uint64_t)h[7] != rle_nblocks((int64_t)w * hh))
       err = CMP_ECORRUPT;
@@ -454,7 +474,8 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
     return;
   }
   const int32_t rw = (int32_t)h[3], rh = (int32_t)h[4];
-  const int np = (int)h[5];
+  const int np = (int)(h[5] & 0xFFu);
+  const bool swizzled = (h[5] >> 8) & 1u;
   const uint64_t nb = h[7];
   if (b == 0 && a.roi_out && tid == 0)
     reinterpret_cast<int4*>(a.roi_out)[s] = int4{(int)h[1], (int)h[2], (int)h[3], (int)h[4]};
@@ -580,6 +601,10 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
     if (tid == 0) a.status[s] = CMP_ECORRUPT;
     return;
   }
+  if (swizzled) {
+#pragma unroll
+    for (int j = 0; j < kPxPerLane; ++j) col[j] = swizzle_bits(col[j]);
+  }
   // ---- write the pixels (row-major over the ROI)
   if (q0 < len) {
     const int64_t q = (int64_t)b * kBlock + q0;
@@ -641,7 +666,7 @@ extern "C" size_t cmp_rle_workspace_size(const cmp_image* imgs, int32_t n) {
 }
 
 extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_format fmt,
-                                       const int32_t* roi_dev, uint8_t* const* out,
+                                       uint32_t flags, const int32_t* roi_dev, uint8_t* const* out,
                                        const uint64_t* capacity, uint64_t* out_size_dev,
                                        int32_t* status_dev, void* workspace, size_t ws_bytes,
                                        void* stream) {
@@ -652,12 +677,13 @@ extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_for
     return CMP_EUNSUPPORTED;
   }
   CMP_REQUIRE(imgs && out && capacity && out_size_dev && workspace, "NULL argument");
+  CMP_REQUIRE((flags & ~CMP_RLE_SWIZZLE) == 0, "unknown flags 0x%x", flags);
   CMP_REQUIRE(((uintptr_t)roi_dev & 15) == 0 && ((uintptr_t)workspace & 15) == 0 &&
                   ((uintptr_t)out_size_dev & 7) == 0,
               "roi_dev/workspace must be 16-byte and out_size_dev 8-byte aligned");
   RleCArgs a;
   memset(&a, 0, sizeof a);
-  int64_t grid = 0, flags = 0;
+  int64_t grid = 0, nflags = 0;
   for (int i = 0; i < n; ++i) {
     const cmp_image& I = imgs[i];
     CMP_REQUIRE(rect_valid(I.roi), "imgs[%d] has a negative size", i);
@@ -677,12 +703,12 @@ extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_for
       return CMP_ENOSPC;
     }
     const int64_t nb = (int64_t)rle_nblocks((int64_t)W * H);
-    a.im[i] = RleCImg{(const uint32_t*)I.color, I.depth, I.pitch, W, H, out[i], (int32_t)flags, 0};
-    flags += nb ? nb : 1;
+    a.im[i] = RleCImg{(const uint32_t*)I.color, I.depth, I.pitch, W, H, out[i], (int32_t)nflags, 0};
+    nflags += nb ? nb : 1;
     grid += nb ? nb : 1;
   }
   CMP_REQUIRE(grid < (1ll << 24), "too many blocks");
-  const size_t need = (size_t)(64 + 8 * flags);
+  const size_t need = (size_t)(64 + 8 * nflags);
   if (ws_bytes < need) {
     set_error("workspace of %zu bytes is smaller than %zu", ws_bytes, need);
     return CMP_ENOSPC;
@@ -693,6 +719,7 @@ extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_for
   a.ctl = (uint32_t*)workspace;
   a.flags = (uint64_t*)((char*)workspace + 64);
   a.n = n;
+  a.swizzle = (flags & CMP_RLE_SWIZZLE) ? 1 : 0;
   hipLaunchKernelGGL(rle_compress_kernel, dim3((unsigned)grid), dim3(kThreads), 0,
                      (hipStream_t)stream, a);
   CMP_CHECK_HIP(hipGetLastError());

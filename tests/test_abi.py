@@ -155,15 +155,15 @@ def test_roi_and_rle_argument_errors():
     need = cmp.rle_max_size(64, 64, 8)
     caps = (ctypes.c_uint64 * 2)(need, need - 1)
     wsz = L.cmp_rle_workspace_size(imgs, 2)
-    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA8, None, outs, caps, 0x3000, None, 0x4000, wsz,
+    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA8, 0, None, outs, caps, 0x3000, None, 0x4000, wsz,
                               None) == cmp.CMP_ENOSPC
     caps[1] = need
-    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA8, None, outs, caps, 0x3000, None, 0x4000, wsz - 8,
+    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA8, 0, None, outs, caps, 0x3000, None, 0x4000, wsz - 8,
                               None) == cmp.CMP_ENOSPC
-    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA32F, None, outs, caps, 0x3000, None, 0x4000, wsz,
+    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA32F, 0, None, outs, caps, 0x3000, None, 0x4000, wsz,
                               None) == cmp.CMP_EUNSUPPORTED
     bad = (ctypes.c_void_p * 2)(0x100008, 0x200000)
-    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA8, None, bad, caps, 0x3000, None, 0x4000, wsz,
+    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA8, 0, None, bad, caps, 0x3000, None, 0x4000, wsz,
                               None) == cmp.CMP_EINVAL
     ins = (ctypes.c_void_p * 1)(0x100004)
     nb = (ctypes.c_uint64 * 1)(100)

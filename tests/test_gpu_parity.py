@@ -558,3 +558,32 @@ def test_ramp_pipeline_full_size():
     # cropping is lossless: the same as compositing the full frames
     full_c, full_d = _oracle_depth(wl.images, wl.viewport)
     assert (ref_c == full_c).all() and (ref_d == full_d).all()
+
+
+def test_rle_swizzled_streams():
+    """Bit-swizzled colour planes: byte-identical streams and round trips."""
+    wl = synth.depth_ramps_full(seed=2, n=4, W=640, H=360, device=DEV)
+    rng = np.random.default_rng(8)
+    noise = torch.from_numpy(rng.integers(0, 2 ** 32, (90, 200), dtype=np.uint64)
+                             .astype(np.uint32).view(np.int32)).to(DEV)
+    imgs = list(wl.images) + [cmp.Image(noise, noise.clone(), (0, 0, 200, 90)),
+                              cmp.Image(noise.clone(), None, (0, 0, 200, 90))]
+    roi = cmp.roi_detect(imgs[:4])
+    rois = [tuple(r) for r in roi.cpu().tolist()] + [(3, 4, 190, 81), (0, 0, 200, 90)]
+    rd = torch.tensor(rois, dtype=torch.int32, device=DEV)
+    note("rle swizzled")
+    streams, sizes = cmp.rle_compress(imgs, roi_dev=rd, swizzle=True)
+    torch.cuda.synchronize()
+    for k, im in enumerate(imgs):
+        c = u32(im.color)
+        d = u32(im.depth) if im.depth is not None else None
+        ref = oracle.rle_compress(c, d, rois[k], swizzle=True)
+        n = int(sizes[k])
+        assert n == ref.size and (streams[k][:n].cpu().numpy() == ref).all(), k
+    outs = [cmp.Image(torch.zeros_like(im.color), None if im.depth is None else torch.zeros_like(im.depth),
+                      im.roi) for im in imgs]
+    _, st = cmp.rle_decompress(streams, outs)
+    torch.cuda.synchronize()
+    assert (st == 0).all()
+    for im, o, (x, y, w, h) in zip(imgs, outs, rois):
+        assert torch.equal(o.color[:h, :w], im.color[y:y + h, x:x + w])
