@@ -60,7 +60,8 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const BatchArgs a) {
   __shared__ int s_item;
   const int tid = threadIdx.x;
   while (true) {
-    if (tid == 0) s_item = (int)atomicAdd(&a.ctl[0], 1u);
+    if (tid == 0)
+      s_item = (int)__hip_atomic_fetch_add(&a.ctl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const int it = uniform(s_item);
     __syncthreads();
@@ -86,8 +87,9 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const BatchArgs a) {
     }
   }
   if (tid == 0) {
-    __threadfence();
-    const uint32_t done = atomicAdd(&a.ctl[1], 1u);
+    // no fence: nothing but the counters is shared with the last workgroup
+    const uint32_t done =
+        __hip_atomic_fetch_add(&a.ctl[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (done == gridDim.x - 1) {
       __hip_atomic_store(&a.ctl[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&a.ctl[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -432,8 +434,8 @@ extern "C" cmp_status cmp_autotune(const cmp_job* jobs, int32_t njobs, const cha
     }
     out.push_back(best);
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (st != CMP_OK) return st;
   FILE* f = fopen(cache_path, "w");
   if (!f) {

@@ -167,20 +167,41 @@ __global__ __launch_bounds__(kThreads) void rle_compress_kernel(const RleCArgs a
   const uint32_t ticket = s_ticket, epoch = s_epoch;
 
   // ticket -> (image, block); an image with an empty ROI still takes one
-  // ticket, whose workgroup writes its header-only stream
+  // ticket, whose workgroup writes its header-only stream. Lane i of every
+  // wave looks at image i (n <= 64): one load, then a wave scan of the slots.
   int s = -1, b = 0, rx = 0, ry = 0, rw = 0, rh = 0;
   {
-    uint32_t t = ticket;
-    for (int i = 0; i < a.n; ++i) {
-      int x, y, w, h;
-      clamp_roi(a.roi_dev, i, a.im[i].W, a.im[i].H, x, y, w, h);
-      const uint32_t nb = (uint32_t)rle_nblocks((int64_t)w * h);
-      const uint32_t slots = nb ? nb : 1;
-      if (t < slots) {
-        s = i; b = (int)t; rx = x; ry = y; rw = w; rh = h;
-        break;
+    int x = 0, y = 0, w = 0, h = 0;
+    uint32_t slots = 0;
+    if (lane < a.n) {
+      const int W = a.im[lane].W, H = a.im[lane].H;
+      if (a.roi_dev) {
+        const int4 r = reinterpret_cast<const int4*>(a.roi_dev)[lane];
+        x = min(max(r.x, 0), W);
+        y = min(max(r.y, 0), H);
+        w = min(max(r.z, 0), W - x);
+        h = min(max(r.w, 0), H - y);
+        if (w == 0 || h == 0) { x = 0; y = 0; w = 0; h = 0; }
+      } else {
+        w = W; h = H;
       }
-      t -= slots;
+      const uint32_t nb = (uint32_t)rle_nblocks((int64_t)w * h);
+      slots = nb ? nb : 1;
+    }
+    uint32_t incl = slots;   // inclusive scan of the slots over the lanes
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint32_t o = __shfl_up(incl, d);
+      if (lane >= d) incl += o;
+    }
+    const uint64_t hit = __ballot(lane < a.n && ticket < incl);
+    if (hit) {
+      const int i = __builtin_ctzll(hit);
+      s = i;
+      b = (int)(ticket - (__shfl(incl, i) - __shfl(slots, i)));
+      rx = __shfl(x, i); ry = __shfl(y, i); rw = __shfl(w, i); rh = __shfl(h, i);
+      s = uniform(s); b = uniform(b); rx = uniform(rx); ry = uniform(ry);
+      rw = uniform(rw); rh = uniform(rh);
     }
   }
   if (s >= 0) {
@@ -399,10 +420,11 @@ __global__ __launch_bounds__(kThreads) void rle_compress_kernel(const RleCArgs a
     }
   }
   // ---- completion: the last workgroup resets the counters for the next call
+  // (no fence: nothing but the counters is shared with that workgroup)
   __syncthreads();
   if (tid == 0) {
-    __threadfence();
-    const uint32_t done = atomicAdd(&a.ctl[1], 1u);
+    const uint32_t done =
+        __hip_atomic_fetch_add(&a.ctl[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (done == gridDim.x - 1) {
       __hip_atomic_store(&a.ctl[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&a.ctl[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -3,11 +3,13 @@
 //
 // One pass over every image, several images per launch. A workgroup scans a
 // band of rows with 16-byte loads (4 depth or RGBA8 pixels, 2 RGBA16F pixels
-// or 1 RGBA32F pixel per load), keeps per-lane min/max of the data pixels'
-// columns and rows, reduces them across the wave and the workgroup, and
-// stores one partial box. The last workgroup of an image (counted with an
-// atomic ticket) folds the partial boxes into the final rectangle and resets
-// the ticket, so the workspace is ready for the next call.
+// or 1 RGBA32F pixel per load, several in flight per lane), keeps per-lane
+// min/max of the data pixels' columns and rows, reduces them across the wave
+// and the workgroup, and folds the box into the image's accumulator with
+// device-scope atomic maxima. The last workgroup of an image (counted with an
+// atomic ticket) turns the accumulator into the rectangle and clears it and
+// the ticket, so the workspace is ready for the next call. No fence is
+// needed: every access to the shared words is a device-scope atomic.
 #include <string.h>
 
 #include "cmp_internal.hpp"
@@ -16,6 +18,8 @@ namespace cmp {
 
 constexpr int kRoiMax = 64;
 constexpr int kRoiBatch = 8;
+// workspace: int32 tickets[64] (256 bytes), then int32 accumulators[64][4]
+constexpr size_t kRoiWorkspace = 256 + 64 * 16;
 
 struct RoiImg {
   const void* color;
@@ -25,14 +29,14 @@ struct RoiImg {
   int32_t wg_begin;   // first workgroup of this image
   int32_t nwg;        // workgroups of this image
   int32_t rows;       // rows per workgroup
-  int32_t part_base;  // first partial slot
+  int32_t pad;
 };
 
 struct RoiArgs {
   RoiImg im[kRoiMax];
   int32_t* roi_out;
-  int32_t* ticket;    // workspace: int32[n]
-  int4* part;         // workspace: int4[total workgroups]
+  int32_t* ticket;    // workspace: int32[64] tickets
+  int32_t* acc;       // workspace: int32[64][4] box accumulators
   int32_t n;
   int32_t mode;       // 0 depth, 1 RGBA8 colour, 2 RGBA32F, 3 RGBA16F
 };
@@ -135,7 +139,6 @@ __global__ __launch_bounds__(kThreads) void roi_kernel(const RoiArgs a) {
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   if (lane == 0) red[wave] = int4{minx, miny, maxx, maxy};
   __syncthreads();
-  __shared__ int last;
   if (threadIdx.x == 0) {
     int4 b = red[0];
 #pragma unroll
@@ -145,43 +148,33 @@ __global__ __launch_bounds__(kThreads) void roi_kernel(const RoiArgs a) {
       b.z = max(b.z, red[w].z);
       b.w = max(b.w, red[w].w);
     }
-    a.part[I.part_base + local] = b;
-    __threadfence();
-    const int t = atomicAdd(&a.ticket[s], 1);
-    last = (t == I.nwg - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // fold the partial boxes of image s
-  int4 b = int4{0x7FFFFFFF, 0x7FFFFFFF, -1, -1};
-  for (int k = threadIdx.x; k < I.nwg; k += kThreads) {
-    const int4 p = a.part[I.part_base + k];
-    b.x = min(b.x, p.x);
-    b.y = min(b.y, p.y);
-    b.z = max(b.z, p.z);
-    b.w = max(b.w, p.w);
-  }
-  b.x = wave_min(b.x);
-  b.y = wave_min(b.y);
-  b.z = wave_max(b.z);
-  b.w = wave_max(b.w);
-  __syncthreads();
-  if (lane == 0) red[wave] = b;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    b = red[0];
-#pragma unroll
-    for (int w = 1; w < kThreads / kWave; ++w) {
-      b.x = min(b.x, red[w].x);
-      b.y = min(b.y, red[w].y);
-      b.z = max(b.z, red[w].z);
-      b.w = max(b.w, red[w].w);
+    // fold into the image's accumulator with device-scope atomic maxima; the
+    // encoding (INT_MAX - min, max + 1) makes a zeroed accumulator the empty
+    // box. No fence: the atomics complete (s_waitcnt) before the ticket.
+    int* acc = a.acc + 4 * s;
+    if (b.z >= 0) {
+      __hip_atomic_fetch_max(&acc[0], 0x7FFFFFFF - b.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_max(&acc[1], 0x7FFFFFFF - b.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_max(&acc[2], b.z + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_max(&acc[3], b.w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    int4 r = int4{0, 0, 0, 0};
-    if (b.z >= 0) r = int4{b.x, b.y, b.z - b.x + 1, b.w - b.y + 1};
-    reinterpret_cast<int4*>(a.roi_out)[s] = r;
-    a.ticket[s] = 0;
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    const int t = __hip_atomic_fetch_add(&a.ticket[s], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t == I.nwg - 1) {   // the image's last workgroup
+      const int ax = __hip_atomic_load(&acc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int ay = __hip_atomic_load(&acc[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int az = __hip_atomic_load(&acc[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int aw = __hip_atomic_load(&acc[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int4 r = int4{0, 0, 0, 0};
+      if (az > 0) {
+        const int x0 = 0x7FFFFFFF - ax, y0 = 0x7FFFFFFF - ay;
+        r = int4{x0, y0, az - x0, aw - y0};
+      }
+      reinterpret_cast<int4*>(a.roi_out)[s] = r;
+      for (int k = 0; k < 4; ++k)
+        __hip_atomic_store(&acc[k], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&a.ticket[s], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
@@ -196,33 +189,13 @@ static int roi_rows(const cmp_image& I, int bpp) {
 
 static int roi_bpp(cmp_format fmt) { return fmt == CMP_RGBA32F ? 16 : fmt == CMP_RGBA16F ? 8 : 4; }
 
-// Workspace: int32 tickets[64] (256 bytes), then one int4 per workgroup.
-static int64_t roi_total_wg(const cmp_image* imgs, int32_t n, cmp_format fmt) {
-  int64_t total = 0;
-  for (int i = 0; i < n; ++i) {
-    const cmp_image& I = imgs[i];
-    if (I.roi.w <= 0 || I.roi.h <= 0) {
-      total += 1;
-      continue;
-    }
-    const int rows = roi_rows(I, roi_bpp(fmt));
-    total += (I.roi.h + rows - 1) / rows;
-  }
-  return total;
-}
-
 }  // namespace cmp
 
 using namespace cmp;
 
 extern "C" size_t cmp_roi_workspace_size(const cmp_image* imgs, int32_t n) {
   if (n < 0 || (n > 0 && !imgs)) return 0;
-  // the largest of the per-format workgroup counts
-  int64_t wg = roi_total_wg(imgs, n, CMP_RGBA8);
-  const int64_t w2 = roi_total_wg(imgs, n, CMP_RGBA32F), w3 = roi_total_wg(imgs, n, CMP_RGBA16F);
-  if (w2 > wg) wg = w2;
-  if (w3 > wg) wg = w3;
-  return (size_t)(256 + 16 * wg);
+  return kRoiWorkspace;
 }
 
 extern "C" cmp_status cmp_roi_detect(const cmp_image* imgs, int32_t n, cmp_format fmt,
@@ -260,18 +233,18 @@ extern "C" cmp_status cmp_roi_detect(const cmp_image* imgs, int32_t n, cmp_forma
     const int rows = empty ? 1 : roi_rows(I, bpp);
     const int nwg = empty ? 1 : (I.roi.h + rows - 1) / rows;
     a.im[i] = RoiImg{I.color, I.depth, I.pitch, empty ? 0 : I.roi.w, empty ? 0 : I.roi.h,
-                     (int32_t)wg, nwg, rows, (int32_t)wg};
+                     (int32_t)wg, nwg, rows, 0};
     wg += nwg;
   }
   CMP_REQUIRE(wg < (1 << 24), "too many workgroups");
-  const size_t need = (size_t)(256 + 16 * wg);
+  const size_t need = kRoiWorkspace;
   if (ws_bytes < need) {
     set_error("workspace of %zu bytes is smaller than %zu", ws_bytes, need);
     return CMP_ENOSPC;
   }
   a.roi_out = roi_out_dev;
   a.ticket = (int32_t*)workspace;
-  a.part = (int4*)((char*)workspace + 256);
+  a.acc = (int32_t*)((char*)workspace + 256);
   a.n = n;
   a.mode = mode;
   hipStream_t s = (hipStream_t)stream;
