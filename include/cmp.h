@@ -85,8 +85,8 @@ typedef struct { int32_t kind; int32_t owners; } cmp_schedule;
  * (host) and returns how many there are, or a negative cmp_status. Host-only. */
 int32_t cmp_schedule_regions(cmp_schedule sched, cmp_rect viewport, cmp_rect* out, int32_t max);
 
-/* Workgroup tile in destination pixels; {0, 0} picks the default. tile_w must
- * be a multiple of 4 for depth compositing. The tile never changes results. */
+/* Workgroup tile in destination pixels; {0, 0} picks the default. Widths that
+ * are multiples of 64 keep every lane busy. The tile never changes results. */
 typedef struct { int32_t w, h; } cmp_tile;
 
 /* One contributor image or layer. */
@@ -232,9 +232,9 @@ size_t cmp_rle_max_size(int32_t w, int32_t h, int32_t nplanes);
  *   out_size_dev  device uint64[n]: the stream sizes.
  *   status_dev    NULL or device int32[n]; a bounded wait that gives up
  *                 stores CMP_ETIMEOUT there (never expected).
- *   workspace     device, >= cmp_rle_workspace_size(imgs, n) bytes,
- *                 zero-filled before its first use; calls leave it ready for
- *                 the next call. Calls sharing a workspace must not overlap.
+ *   workspace     device, >= cmp_rle_workspace_size(imgs, n) bytes; needs no
+ *                 initialisation (each call clears what it uses). Calls
+ *                 sharing a workspace must not overlap.
  * n <= 64. Errors: CMP_EINVAL, CMP_ENOSPC, CMP_EUNSUPPORTED, CMP_EHIP.
  */
 size_t     cmp_rle_workspace_size(const cmp_image* imgs, int32_t n);

@@ -101,8 +101,8 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const BatchArgs a) {
 struct TileShape {
   int w, h;
 };
-static const TileShape kDepthTiles[] = {{64, 16}, {128, 8}, {256, 4}, {32, 32}, {64, 32},
-                                        {128, 16}, {256, 16}};
+static const TileShape kDepthTiles[] = {{64, 16}, {64, 32}, {64, 64}, {128, 16}, {128, 32},
+                                        {256, 16}};
 static const TileShape kOverTiles[] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}, {64, 8},
                                        {16, 16}, {64, 16}, {128, 8}};
 static const TileShape kDepthDefault = {64, 16}, kOverDefault = {64, 8};

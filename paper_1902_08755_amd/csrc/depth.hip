@@ -86,8 +86,8 @@ extern "C" cmp_status cmp_composite_depth(const cmp_image* in, int32_t n, const 
               kDepthPerPass);
   CMP_REQUIRE(((uintptr_t)roi_dev & 15) == 0, "roi_dev must be 16-byte aligned");
   const int tw = tile.w ? tile.w : 64, th = tile.h ? tile.h : 16;
-  CMP_REQUIRE(tw % 4 == 0 && tw > 0 && th > 0 && (int64_t)tw * th <= 65536,
-              "tile %dx%d: width must be a positive multiple of 4, area <= 65536", tw, th);
+  CMP_REQUIRE(tw > 0 && th > 0 && (int64_t)tw * th <= 65536,
+              "tile %dx%d: sizes must be positive, area <= 65536", tw, th);
 
   DepthArgs a;
   memset(&a, 0, sizeof a);

@@ -15,18 +15,20 @@
 //     starts over the following lanes of the same 256-pixel segment;
 //   - the encoded block is staged in LDS, and its payload offset comes from a
 //     decoupled look-back over the blocks of the image (Merrill and Garland,
-//     "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016).
-//     Blocks are claimed with an atomic ticket, so every predecessor a block
-//     waits for is already running; the wait is bounded all the same.
-// The ticket, a completion counter and an epoch that tags the look-back
-// flags of one call live in the caller's workspace; the last workgroup
-// resets the counters and advances the epoch, so no clearing is needed
-// between calls.
+//     "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016),
+//     one wave reading 64 predecessors' flags at a time.
+// The grid is at most one resident wave of workgroups, each taking the slots
+// (image, block) w, w + G, ... in a fixed order, so no ticket counter is
+// needed: the smallest unfinished slot always belongs to a running
+// workgroup. A small kernel clears the look-back flags before each call.
+// Every workgroup derives the slot count from the device ROIs, so blocks that
+// the ROIs leave out cost nothing.
 //
-// Decompression: a workgroup decodes one block: header and table checks,
-// payload to LDS, per plane a scan of the run lengths and, per lane, a binary
-// search for its first run; pixels are assembled in registers and written
-// with 16-byte stores.
+// Decompression: a grid-stride loop over the blocks of all streams (counted
+// from the stream headers); per block: header and table checks, payload to
+// LDS, per plane a scan of the run lengths and, per lane, a binary search for
+// its first run; pixels are assembled in registers and written with 16-byte
+// stores.
 #include <string.h>
 
 #include "cmp_internal.hpp"
@@ -140,71 +142,86 @@ struct RleCArgs {
   const int32_t* roi_dev;
   uint64_t* out_size;
   int32_t* status;
-  uint32_t* ctl;           // workspace: [0] ticket, [1] done, [2] epoch
   uint64_t* flags;         // workspace: one flag per (image, block)
   int32_t n;
   int32_t swizzle;         // CMP_RLE_SWIZZLE
 };
 static_assert(sizeof(RleCArgs) <= 4096, "kernel arguments must fit in 4 KiB");
 
-// look-back flag: epoch (30 bits) | status (2 bits) | value (32 bits)
+// look-back flag: status (2 bits) << 32 | value (32 bits); 0 = not ready.
+// The flags are cleared by rle_clear_kernel before every compression.
 constexpr uint64_t kAgg = 1, kIncl = 2;
-__device__ __forceinline__ uint64_t mkflag(uint32_t epoch, uint64_t st, uint32_t v) {
-  return ((uint64_t)(epoch & 0x3FFFFFFFu) << 34) | (st << 32) | v;
+__device__ __forceinline__ uint64_t mkflag(uint64_t st, uint32_t v) { return (st << 32) | v; }
+
+__global__ __launch_bounds__(kThreads) void rle_clear_kernel(uint64_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    p[i] = 0;
 }
 
 __global__ __launch_bounds__(kThreads) void rle_compress_kernel(const RleCArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t stage[kStage];
   __shared__ uint64_t sh[8];
-  __shared__ uint32_t s_ticket, s_epoch, s_excl;
+  __shared__ uint32_t s_excl;
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
-  if (tid == 0) {
-    s_ticket = atomicAdd(&a.ctl[0], 1u);
-    s_epoch = __hip_atomic_load(&a.ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  const uint32_t ticket = s_ticket, epoch = s_epoch;
 
-  // ticket -> (image, block); an image with an empty ROI still takes one
-  // ticket, whose workgroup writes its header-only stream. Lane i of every
-  // wave looks at image i (n <= 64): one load, then a wave scan of the slots.
-  int s = -1, b = 0, rx = 0, ry = 0, rw = 0, rh = 0;
-  {
-    int x = 0, y = 0, w = 0, h = 0;
-    uint32_t slots = 0;
+  // Slots: one per block of every image's ROI (an empty ROI still takes one
+  // slot, whose workgroup writes the header-only stream). Wave 0 computes the
+  // table (lane i: image i, n <= 64; one load, then a wave scan) into LDS.
+  __shared__ int4 t_roi[kRleMax];
+  __shared__ uint32_t t_slots[kRleMax], t_incl[kRleMax], t_total;
+  if (tid < kWave) {
+    int lx = 0, ly = 0, lw = 0, lh = 0;
+    uint32_t lslots = 0;
     if (lane < a.n) {
       const int W = a.im[lane].W, H = a.im[lane].H;
       if (a.roi_dev) {
         const int4 r = reinterpret_cast<const int4*>(a.roi_dev)[lane];
-        x = min(max(r.x, 0), W);
-        y = min(max(r.y, 0), H);
-        w = min(max(r.z, 0), W - x);
-        h = min(max(r.w, 0), H - y);
-        if (w == 0 || h == 0) { x = 0; y = 0; w = 0; h = 0; }
+        lx = min(max(r.x, 0), W);
+        ly = min(max(r.y, 0), H);
+        lw = min(max(r.z, 0), W - lx);
+        lh = min(max(r.w, 0), H - ly);
+        if (lw == 0 || lh == 0) { lx = 0; ly = 0; lw = 0; lh = 0; }
       } else {
-        w = W; h = H;
+        lw = W; lh = H;
       }
-      const uint32_t nb = (uint32_t)rle_nblocks((int64_t)w * h);
-      slots = nb ? nb : 1;
+      const uint32_t nb = (uint32_t)rle_nblocks((int64_t)lw * lh);
+      lslots = nb ? nb : 1;
     }
-    uint32_t incl = slots;   // inclusive scan of the slots over the lanes
+    uint32_t lincl = lslots;
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
-      const uint32_t o = __shfl_up(incl, d);
-      if (lane >= d) incl += o;
+      const uint32_t o = __shfl_up(lincl, d);
+      if (lane >= d) lincl += o;
     }
-    const uint64_t hit = __ballot(lane < a.n && ticket < incl);
-    if (hit) {
-      const int i = __builtin_ctzll(hit);
-      s = i;
-      b = (int)(ticket - (__shfl(incl, i) - __shfl(slots, i)));
-      rx = __shfl(x, i); ry = __shfl(y, i); rw = __shfl(w, i); rh = __shfl(h, i);
-      s = uniform(s); b = uniform(b); rx = uniform(rx); ry = uniform(ry);
-      rw = uniform(rw); rh = uniform(rh);
-    }
+    t_roi[lane] = int4{lx, ly, lw, lh};
+    t_slots[lane] = lslots;
+    t_incl[lane] = lincl;
+    if (lane == kWave - 1) t_total = lincl;
   }
-  if (s >= 0) {
+  __syncthreads();
+  const uint32_t total = t_total;
+
+  // Slots are taken in a fixed order: workgroup w does slots w, w + G, ...
+  // A block waits only for smaller slots of its image; the smallest
+  // unfinished slot always belongs to a running workgroup that has finished
+  // its earlier slots, so the waits always end (and are bounded anyway).
+  for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
+  // an opaque copy of the thread index: keeps per-lane values from being
+  // hoisted out of the loop and held in registers across iterations
+  int tid = threadIdx.x;
+  __asm__ volatile("" : "+v"(tid));
+  const int lane = tid % kWave;
+  int s, b, rx, ry, rw, rh;
+  {
+    const uint64_t hit = __ballot(lane < a.n && g < t_incl[lane]);
+    s = uniform(__builtin_ctzll(hit));
+    b = uniform((int)(g - (t_incl[s] - t_slots[s])));
+    const int4 r = t_roi[s];
+    rx = uniform(r.x); ry = uniform(r.y); rw = uniform(r.z); rh = uniform(r.w);
+  }
+  {
     const RleCImg I = a.im[s];
     const int np = I.depth ? 8 : 4;
     const int64_t npx = (int64_t)rw * rh;
@@ -330,9 +347,23 @@ __global__ __launch_bounds__(kThreads) void rle_compress_kernel(const RleCArgs a
               const uint32_t rest = m >> (j + 1);
               const int end = rest ? q0 + j + 1 + __builtin_ctz(rest) : next_after;
               const uint32_t idx = tok0 + __builtin_popcount(m & ((1u << j) - 1u));
-              stage[off + 2 * idx] = (uint8_t)(end - (q0 + j) - 1);
-              stage[off + 2 * idx + 1] = (uint8_t)byte_of(w[j], k);
+              const uint32_t tokv = (uint32_t)(end - (q0 + j) - 1) | (byte_of(w[j], k) << 8);
+              if ((off & 1u) == 0) {   // uniform: one 16-bit store per token
+                *reinterpret_cast<uint16_t*>(stage + off + 2 * idx) = (uint16_t)tokv;
+              } else {
+                stage[off + 2 * idx] = (uint8_t)tokv;
+                stage[off + 2 * idx + 1] = (uint8_t)(tokv >> 8);
+              }
             }
+          }
+        } else if ((off & 3u) == 0 && q0 + kPxPerLane <= len) {
+          // raw plane, 4-byte aligned: four 32-bit stores per lane
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const uint32_t word = byte_of(w[4 * v], k) | (byte_of(w[4 * v + 1], k) << 8) |
+                                  (byte_of(w[4 * v + 2], k) << 16) |
+                                  (byte_of(w[4 * v + 3], k) << 24);
+            *reinterpret_cast<uint32_t*>(stage + off + q0 + 4 * v) = word;
           }
         } else {
 #pragma unroll
@@ -347,24 +378,23 @@ __global__ __launch_bounds__(kThreads) void rle_compress_kernel(const RleCArgs a
       // nearest inclusive prefix, and moves the window back if it has none
       if (tid < kWave) {
         uint64_t* flags = a.flags + I.flag_base;
-        const uint32_t ep = epoch & 0x3FFFFFFFu;
         uint32_t excl = 0;
         if (b == 0) {
           if (lane == 0)
-            __hip_atomic_store(&flags[0], mkflag(epoch, kIncl, padded), __ATOMIC_RELAXED,
+            __hip_atomic_store(&flags[0], mkflag(kIncl, padded), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         } else {
           if (lane == 0)
-            __hip_atomic_store(&flags[b], mkflag(epoch, kAgg, padded), __ATOMIC_RELAXED,
+            __hip_atomic_store(&flags[b], mkflag(kAgg, padded), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
           int top = b - 1;   // lane l reads predecessor top - l
           uint32_t spins = 0;
           while (true) {
             const int p = top - lane;
-            uint64_t f = mkflag(epoch, kIncl, 0);   // before block 0: an empty prefix
+            uint64_t f = mkflag(kIncl, 0);   // before block 0: an empty prefix
             if (p >= 0) f = __hip_atomic_load(&flags[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint64_t st = (f >> 32) & 3u;
-            const bool ready = ((uint32_t)(f >> 34) == ep) && st != 0;
+            const bool ready = st != 0;
             const uint64_t incl = __ballot(ready && st == kIncl);
             const uint64_t notready = __ballot(!ready);
             const int first = incl ? __builtin_ctzll(incl) : kWave;
@@ -385,7 +415,7 @@ __global__ __launch_bounds__(kThreads) void rle_compress_kernel(const RleCArgs a
             top -= kWave;
           }
           if (lane == 0)
-            __hip_atomic_store(&flags[b], mkflag(epoch, kIncl, excl + padded), __ATOMIC_RELAXED,
+            __hip_atomic_store(&flags[b], mkflag(kIncl, excl + padded), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
         if (lane == 0) s_excl = excl;
@@ -419,18 +449,7 @@ __global__ __launch_bounds__(kThreads) void rle_compress_kernel(const RleCArgs a
       for (uint32_t i = tid; i < padded / 16; i += kThreads) dst[i] = src[i];
     }
   }
-  // ---- completion: the last workgroup resets the counters for the next call
-  // (no fence: nothing but the counters is shared with that workgroup)
-  __syncthreads();
-  if (tid == 0) {
-    const uint32_t done =
-        __hip_atomic_fetch_add(&a.ctl[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (done == gridDim.x - 1) {
-      __hip_atomic_store(&a.ctl[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&a.ctl[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&a.ctl[2], (epoch + 1u) & 0x3FFFFFFFu, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    }
+  __syncthreads();   // the stage and the scan words are reused by the next slot
   }
 }
 
@@ -442,7 +461,6 @@ struct RleDImg {
   uint32_t* depth;
   int64_t pitch;
   int32_t cap_w, cap_h;
-  int32_t wg_begin, nwg;
 };
 
 struct RleDArgs {
@@ -462,38 +480,72 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
   __shared__ uint32_t s_boff, s_next;
   __shared__ int32_t s_err;
   const int tid = threadIdx.x;
-  const int blk = blockIdx.x;
-  int s = 0;
-  while (s + 1 < a.n && a.im[s + 1].wg_begin <= blk) ++s;
-  const RleDImg I = a.im[s];
-  const int b = blk - I.wg_begin;
+  const int lane = tid % kWave;
 
-  // ---- header (every lane reads it: one broadcast load) and this block's
-  // table entries (one lane per entry)
-  uint32_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int err = 0;
-  if (I.in_bytes < 32) {
-    err = CMP_ECORRUPT;
-  } else {
-    const u32x4 h0 = reinterpret_cast<const u32x4*>(I.in)[0];
-    const u32x4 h1 = reinterpret_cast<const u32x4*>(I.in)[1];
-    h[0] = h0.x; h[1] = h0.y; h[2] = h0.z; h[3] = h0.w;
-    h[4] = h1.x; h[5] = h1.y; h[6] = h1.z; h[7] = h1.w;
-    const int32_t w = (int32_t)h[3], hh = (int32_t)h[4];
-    const uint32_t np = h[5] & 0xFFu;
-    if (h[0] != kRleMagic || w < 0 || hh < 0 || (np != 4 && np != 8) || h[6] != (uint32_t)kBlock ||
-        (h[5] & ~0x1FFu))
-      err = CMP_ECORRUPT;
-    else if ((uint64_t)h[7] != rle_nblocks((int64_t)w * hh))
-      err = CMP_ECORRUPT;
-    else if (I.in_bytes < rle_p0(h[7], (int)np))
-      err = CMP_ECORRUPT;
-    else if (w > I.cap_w || hh > I.cap_h || (np == 8 && !I.depth))
-      err = CMP_ENOSPC;
+  // Wave 0 reads and checks the header of stream i in lane i (n <= 64) into
+  // LDS; a stream takes one slot per block, or one slot if it has no blocks
+  // or a bad header (that slot reports the status or writes the ROI).
+  __shared__ uint32_t t_hdr[kRleMax][8];
+  __shared__ int32_t t_err[kRleMax];
+  __shared__ uint32_t t_slots[kRleMax], t_incl[kRleMax], t_total;
+  if (tid < kWave) {
+    uint32_t lh[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int lerr = 0;
+    uint32_t lslots = 0;
+    if (lane < a.n) {
+      const RleDImg& I = a.im[lane];
+      if (I.in_bytes < 32) {
+        lerr = CMP_ECORRUPT;
+      } else {
+        const u32x4 h0 = reinterpret_cast<const u32x4*>(I.in)[0];
+        const u32x4 h1 = reinterpret_cast<const u32x4*>(I.in)[1];
+        lh[0] = h0.x; lh[1] = h0.y; lh[2] = h0.z; lh[3] = h0.w;
+        lh[4] = h1.x; lh[5] = h1.y; lh[6] = h1.z; lh[7] = h1.w;
+        const int32_t w = (int32_t)lh[3], hh = (int32_t)lh[4];
+        const uint32_t np = lh[5] & 0xFFu;
+        if (lh[0] != kRleMagic || w < 0 || hh < 0 || (np != 4 && np != 8) ||
+            lh[6] != (uint32_t)kBlock || (lh[5] & ~0x1FFu))
+          lerr = CMP_ECORRUPT;
+        else if ((uint64_t)lh[7] != rle_nblocks((int64_t)w * hh))
+          lerr = CMP_ECORRUPT;
+        else if (I.in_bytes < rle_p0(lh[7], (int)np))
+          lerr = CMP_ECORRUPT;
+        else if (w > I.cap_w || hh > I.cap_h || (np == 8 && !I.depth))
+          lerr = CMP_ENOSPC;
+      }
+      lslots = (lerr || lh[7] == 0) ? 1u : lh[7];
+    }
+    uint32_t lincl = lslots;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint32_t o = __shfl_up(lincl, d);
+      if (lane >= d) lincl += o;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t_hdr[lane][k] = lh[k];
+    t_err[lane] = lerr;
+    t_slots[lane] = lslots;
+    t_incl[lane] = lincl;
+    if (lane == kWave - 1) t_total = lincl;
   }
+  __syncthreads();
+  const uint32_t total = t_total;
+
+  for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
+  int tid = threadIdx.x;   // opaque per iteration (see the compressor)
+  __asm__ volatile("" : "+v"(tid));
+  const int lane = tid % kWave;
+  const uint64_t hit = __ballot(lane < a.n && g < t_incl[lane]);
+  const int s = uniform(__builtin_ctzll(hit));
+  const int b = uniform((int)(g - (t_incl[s] - t_slots[s])));
+  const RleDImg I = a.im[s];
+  uint32_t h[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) h[k] = (uint32_t)uniform((int)t_hdr[s][k]);
+  const int err = uniform(t_err[s]);
   if (err) {
-    if (tid == 0 && (b == 0 || err == CMP_ECORRUPT)) a.status[s] = err;
-    return;
+    if (tid == 0) a.status[s] = err;
+    continue;   // uniform; no LDS was touched in this slot
   }
   const int32_t rw = (int32_t)h[3], rh = (int32_t)h[4];
   const int np = (int)(h[5] & 0xFFu);
@@ -501,7 +553,7 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
   const uint64_t nb = h[7];
   if (b == 0 && a.roi_out && tid == 0)
     reinterpret_cast<int4*>(a.roi_out)[s] = int4{(int)h[1], (int)h[2], (int)h[3], (int)h[4]};
-  if ((uint64_t)b >= nb) return;
+  if ((uint64_t)b >= nb) continue;   // uniform: a stream without blocks
   const int64_t npx = (int64_t)rw * rh;
   const int len = (int)imin64(kBlock, npx - (int64_t)b * kBlock);
   const uint32_t* tbl = reinterpret_cast<const uint32_t*>(I.in + 32);
@@ -525,15 +577,18 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
     s_err = e;
   }
   __syncthreads();
-  if (s_err) return;
-  uint32_t size[8], poff[8], total = 0;
+  if (s_err) {
+    __syncthreads();
+    continue;
+  }
+  uint32_t size[8], poff[8], btotal = 0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     size[k] = k < np ? s_size[k] : 0;
-    poff[k] = total;
-    total += size[k];
+    poff[k] = btotal;
+    btotal += size[k];
   }
-  const uint32_t padded = (uint32_t)align16(total);
+  const uint32_t padded = (uint32_t)align16(btotal);
   {
     // the whole block payload to LDS: all loads in flight before the stores
     const u32x4* src = reinterpret_cast<const u32x4*>(I.in + rle_p0(nb, np) + s_boff);
@@ -563,9 +618,14 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
     u32x4 pb;   // this lane's 16 bytes of plane k
     if (size[k] == (uint32_t)len) {
       uint32_t w4[4] = {0, 0, 0, 0};
+      if ((off & 3u) == 0 && q0 + kPxPerLane <= len) {   // aligned: four 32-bit loads
 #pragma unroll
-      for (int j = 0; j < kPxPerLane; ++j)
-        if (q0 + j < len) w4[j >> 2] |= (uint32_t)stage[off + q0 + j] << (8 * (j & 3));
+        for (int v = 0; v < 4; ++v) w4[v] = *reinterpret_cast<const uint32_t*>(stage + off + q0 + 4 * v);
+      } else {
+#pragma unroll
+        for (int j = 0; j < kPxPerLane; ++j)
+          if (q0 + j < len) w4[j >> 2] |= (uint32_t)stage[off + q0 + j] << (8 * (j & 3));
+      }
       pb = u32x4{w4[0], w4[1], w4[2], w4[3]};
     } else {
       // run lengths -> inclusive ends (8 tokens per lane)
@@ -621,7 +681,8 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
   }
   if (bad) {
     if (tid == 0) a.status[s] = CMP_ECORRUPT;
-    return;
+    __syncthreads();
+    continue;
   }
   if (swizzled) {
 #pragma unroll
@@ -654,7 +715,24 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
       }
     }
   }
+  __syncthreads();   // LDS is reused by the next slot
+  }
 }
+
+// Workgroups of `kernel` that fit on the device at once (cached per device).
+static int resident_groups(const void* kernel, int* cache) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
+  if (cache[dev] > 0) return cache[dev];
+  int cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess ||
+      cus <= 0 || per_cu <= 0)
+    return 1024;
+  cache[dev] = cus * per_cu;
+  return cache[dev];
+}
+static int g_compress_groups[64], g_decompress_groups[64];
 
 // Look-back flags: one per block of each image's largest possible ROI.
 static int64_t rle_flag_count(const cmp_image* imgs, int32_t n) {
@@ -684,7 +762,7 @@ extern "C" size_t cmp_rle_max_size(int32_t w, int32_t h, int32_t nplanes) {
 
 extern "C" size_t cmp_rle_workspace_size(const cmp_image* imgs, int32_t n) {
   if (n < 0 || (n > 0 && !imgs)) return 0;
-  return (size_t)(64 + 8 * rle_flag_count(imgs, n));
+  return (size_t)(8 * rle_flag_count(imgs, n));
 }
 
 extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_format fmt,
@@ -730,7 +808,7 @@ extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_for
     grid += nb ? nb : 1;
   }
   CMP_REQUIRE(grid < (1ll << 24), "too many blocks");
-  const size_t need = (size_t)(64 + 8 * nflags);
+  const size_t need = (size_t)(8 * nflags);
   if (ws_bytes < need) {
     set_error("workspace of %zu bytes is smaller than %zu", ws_bytes, need);
     return CMP_ENOSPC;
@@ -738,12 +816,20 @@ extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_for
   a.roi_dev = roi_dev;
   a.out_size = out_size_dev;
   a.status = status_dev;
-  a.ctl = (uint32_t*)workspace;
-  a.flags = (uint64_t*)((char*)workspace + 64);
+  a.flags = (uint64_t*)workspace;
   a.n = n;
   a.swizzle = (flags & CMP_RLE_SWIZZLE) ? 1 : 0;
-  hipLaunchKernelGGL(rle_compress_kernel, dim3((unsigned)grid), dim3(kThreads), 0,
-                     (hipStream_t)stream, a);
+  hipStream_t s = (hipStream_t)stream;
+  // clear the look-back flags (a kernel, so that graph replays clear them too)
+  const int64_t cgrid = (nflags + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(rle_clear_kernel, dim3((unsigned)(cgrid < 1024 ? cgrid : 1024)), dim3(kThreads),
+                     0, s, a.flags, nflags);
+  CMP_CHECK_HIP(hipGetLastError());
+  // at most one resident wave of workgroups: every block a workgroup waits
+  // for belongs to a running workgroup
+  const int64_t cap = resident_groups((const void*)rle_compress_kernel, g_compress_groups);
+  hipLaunchKernelGGL(rle_compress_kernel, dim3((unsigned)(grid < cap ? grid : cap)), dim3(kThreads),
+                     0, s, a);
   CMP_CHECK_HIP(hipGetLastError());
   return CMP_OK;
 }
@@ -770,17 +856,16 @@ extern "C" cmp_status cmp_rle_decompress(const uint8_t* const* in, const uint64_
                   "out[%d]: buffers must be 4-byte aligned", i);
     }
     const int64_t nb = (int64_t)rle_nblocks((int64_t)W * H);
-    const int nwg = (int)(nb ? nb : 1);
-    a.im[i] = RleDImg{in[i], in_bytes[i], (uint32_t*)O.color, (uint32_t*)O.depth, O.pitch, W, H,
-                      (int32_t)grid, nwg};
-    grid += nwg;
+    a.im[i] = RleDImg{in[i], in_bytes[i], (uint32_t*)O.color, (uint32_t*)O.depth, O.pitch, W, H};
+    grid += nb ? nb : 1;
   }
   CMP_REQUIRE(grid < (1ll << 24), "too many blocks");
   a.roi_out = roi_out_dev;
   a.status = status_dev;
   a.n = n;
-  hipLaunchKernelGGL(rle_decompress_kernel, dim3((unsigned)grid), dim3(kThreads), 0,
-                     (hipStream_t)stream, a);
+  const int64_t cap = resident_groups((const void*)rle_decompress_kernel, g_decompress_groups);
+  hipLaunchKernelGGL(rle_decompress_kernel, dim3((unsigned)(grid < cap ? grid : cap)),
+                     dim3(kThreads), 0, (hipStream_t)stream, a);
   CMP_CHECK_HIP(hipGetLastError());
   return CMP_OK;
 }

@@ -106,7 +106,7 @@ def test_depth_argument_errors():
     assert call(ok, 1, vp=cmp.Rect(0, 0, -2, 3)) == cmp.CMP_EINVAL
     assert call(ok, 1, sched=cmp.Schedule(2, 3)) == cmp.CMP_EINVAL
     assert call(ok, 1, sched=cmp.Schedule(9, 1)) == cmp.CMP_EINVAL
-    assert call(ok, 1, tile=(6, 4)) == cmp.CMP_EINVAL
+    assert call(ok, 1, tile=(-4, 4)) == cmp.CMP_EINVAL
     assert call(ok, 1, roi=0x1004) == cmp.CMP_EINVAL   # misaligned device ROI table
     many = _arr([_img((0, 0, 8, 8))] * 49)
     assert call(many, 49, od=None) == cmp.CMP_EINVAL     # multi-pass needs out_depth
