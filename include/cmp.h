@@ -173,6 +173,36 @@ cmp_status cmp_composite_over_backward(const cmp_image* in, int32_t n, cmp_forma
                                        const int64_t* grad_pitch_layers, void* stream);
 
 /*
+ * Subpixel compositing (Section 4.2.3, Subpixel: the default compositing
+ * accumulates and averages all computed fragments of a pixel, reusing the
+ * parallel compositing of sort-last rendering). Each of the n sources gives
+ * one RGBA8 sample per pixel (0 where the pixel lies outside its placement);
+ * per channel out = floor((sum + floor(n / 2)) / n), the mean rounded half
+ * up. Integer arithmetic: every schedule and tile gives the same bits.
+ *   in[n]   host array, color = RGBA8; n <= 64.
+ *   out     device uint32, viewport.w x viewport.h, pitch out_pitch.
+ * Errors: CMP_EINVAL, CMP_EHIP.
+ */
+cmp_status cmp_composite_average(const cmp_image* in, int32_t n, cmp_rect viewport,
+                                 uint32_t* out, int64_t out_pitch, cmp_schedule sched,
+                                 cmp_tile tile, void* stream);
+
+/*
+ * Pixel-compound assembly (Section 4.2.2, Pixel: sources render interleaved
+ * pixels described by a pixel kernel, its 2D size kx x ky and the 2D offset
+ * of the source inside it). Source i holds the destination pixels
+ * (vx + ox_i + kx u, vy + oy_i + ky v) at (u, v) of its RGBA8 image
+ * (in[i].color, in[i].pitch; in[i].roi.w/h give its size, roi.x/y are
+ * ignored). offsets: host int32[n][2] = (ox_i, oy_i). A class that no source
+ * has gives 0; if several sources share a class the lowest index wins.
+ * n <= 64, kx * ky <= 64. Errors: CMP_EINVAL (also a source too small for
+ * its class), CMP_EHIP.
+ */
+cmp_status cmp_assemble_pixels(const cmp_image* in, int32_t n, const int32_t* offsets,
+                               int32_t kx, int32_t ky, cmp_rect viewport, uint32_t* out,
+                               int64_t out_pitch, void* stream);
+
+/*
  * Automatic ROI detection: the 2D bounding box of the pixels that hold data
  * (Section 5.3, Region of Interest: the ROI encloses the rendered data and can
  * be found by analysing the framebuffer).

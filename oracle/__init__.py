@@ -85,6 +85,10 @@ def lib():
         L.orc_rle_header.restype = ctypes.c_int
         L.orc_rle_decompress.argtypes = [P, u64, P, P, i64, ctypes.POINTER(Rect)]
         L.orc_rle_decompress.restype = ctypes.c_int
+        L.orc_composite_average_rgba8.argtypes = [i32, P, P, P, Rect, P, i64]
+        L.orc_composite_average_rgba8.restype = None
+        L.orc_assemble_pixels.argtypes = [i32, P, P, P, P, i32, i32, Rect, P, i64]
+        L.orc_assemble_pixels.restype = None
         _lib = L
     return _lib
 
@@ -299,3 +303,32 @@ def rle_decompress(stream):
     if rc != 0:
         raise CorruptStream("corrupt payload")
     return r.tup(), c, d
+
+
+# ------------------------------------------------------ subpixel / pixel
+def composite_average(colors, rois, viewport):
+    """Subpixel compositing (Section 4.2.3): per-channel mean of the n
+    sources' RGBA8 samples, rounded half up; 0 outside a source's ROI."""
+    n = len(colors)
+    colors = [_contig(c, np.uint32) for c in colors]
+    pitch = np.array([c.shape[1] for c in colors], dtype=np.int64)
+    out = np.zeros((viewport[3], viewport[2]), np.uint32)
+    lib().orc_composite_average_rgba8(n, _ptr_array(colors), _ptr(pitch) if n else None,
+                                      _rects(rois), Rect(*viewport), _ptr(out), viewport[2])
+    return out
+
+
+def assemble_pixels(colors, offsets, kernel, viewport):
+    """Pixel-compound assembly (Section 4.2.2). colors[i] holds the pixels of
+    offset class offsets[i] = (ox, oy) of the kernel (kx, ky)."""
+    n = len(colors)
+    colors = [_contig(c, np.uint32) for c in colors]
+    pitch = np.array([c.shape[1] for c in colors], dtype=np.int64)
+    ox = np.array([o[0] for o in offsets], dtype=np.int32)
+    oy = np.array([o[1] for o in offsets], dtype=np.int32)
+    out = np.zeros((viewport[3], viewport[2]), np.uint32)
+    lib().orc_assemble_pixels(n, _ptr_array(colors), _ptr(pitch) if n else None,
+                              _ptr(ox) if n else None, _ptr(oy) if n else None,
+                              int(kernel[0]), int(kernel[1]), Rect(*viewport), _ptr(out),
+                              viewport[2])
+    return out

@@ -580,3 +580,63 @@ int orc_rle_decompress(const uint8_t* in, uint64_t size, uint32_t* out_color, ui
     if (roi_out) *roi_out = r;
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Subpixel compositing (Section 4.2.3, Subpixel: the default compositing   */
+/* accumulates and averages all the computed fragments of a pixel; it       */
+/* reuses the parallel compositing of sort-last rendering except for this   */
+/* combination step). Readings: each of the n sources supplies one sample   */
+/* per pixel, transparent black (0) where the pixel lies outside its ROI;   */
+/* an RGBA8 channel is the integer mean rounded half up:                    */
+/*     out = floor((sum + floor(n / 2)) / n).                               */
+/* ------------------------------------------------------------------------ */
+void orc_composite_average_rgba8(int32_t n, const uint32_t* const* color, const int64_t* pitch,
+                                 const orc_rect* roi, orc_rect viewport, uint32_t* out,
+                                 int64_t out_pitch)
+{
+    for (int64_t v = 0; v < viewport.h; ++v) {
+        for (int64_t u = 0; u < viewport.w; ++u) {
+            const int64_t X = viewport.x + u, Y = viewport.y + v;
+            uint64_t sum[4] = {0, 0, 0, 0};
+            for (int32_t i = 0; i < n; ++i) {
+                if (!in_rect(roi[i], X, Y)) continue;
+                const uint32_t c = color[i][(Y - roi[i].y) * pitch[i] + (X - roi[i].x)];
+                for (int k = 0; k < 4; ++k) sum[k] += (c >> (8 * k)) & 0xFFu;
+            }
+            uint32_t res = 0;
+            if (n > 0)
+                for (int k = 0; k < 4; ++k) {
+                    const uint64_t mean = (sum[k] + (uint64_t)(n / 2)) / (uint64_t)n;
+                    res |= (uint32_t)mean << (8 * k);
+                }
+            out[v * out_pitch + u] = res;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pixel-compound assembly (Section 4.2.2, Pixel: sources render            */
+/* interleaved pixels given by a pixel kernel, its 2D size and the 2D       */
+/* offset of the source inside it; the destination puts every pixel back). */
+/* Source i holds the destination pixels (vx + ox_i + kx u, vy + oy_i +     */
+/* ky v) at (u, v). Readings: a destination pixel whose offset class no     */
+/* source has gets 0; if several sources share a class, the lowest index   */
+/* wins.                                                                    */
+/* ------------------------------------------------------------------------ */
+void orc_assemble_pixels(int32_t n, const uint32_t* const* color, const int64_t* pitch,
+                         const int32_t* offx, const int32_t* offy, int32_t kx, int32_t ky,
+                         orc_rect viewport, uint32_t* out, int64_t out_pitch)
+{
+    for (int64_t v = 0; v < viewport.h; ++v) {
+        for (int64_t u = 0; u < viewport.w; ++u) {
+            uint32_t val = 0;
+            for (int32_t i = 0; i < n; ++i) {
+                if (u % kx == offx[i] && v % ky == offy[i]) {
+                    val = color[i][(v / ky) * pitch[i] + (u / kx)];
+                    break;
+                }
+            }
+            out[v * out_pitch + u] = val;
+        }
+    }
+}

@@ -83,6 +83,8 @@ def lib() -> ctypes.CDLL:
         "cmp_last_error": ([], ctypes.c_char_p),
         "cmp_schedule_regions": ([Schedule, Rect, ctypes.POINTER(Rect), i32], i32),
         "cmp_composite_depth": ([IMG, i32, P, Rect, P, P, i64, Schedule, Tile, P], i32),
+        "cmp_composite_average": ([IMG, i32, Rect, P, i64, Schedule, Tile, P], i32),
+        "cmp_assemble_pixels": ([IMG, i32, P, i32, i32, Rect, P, i64, P], i32),
         "cmp_composite_over": ([IMG, i32, i32, P, Rect, P, i64, Schedule, Tile, P], i32),
         "cmp_composite_over_backward": ([IMG, i32, i32, P, Rect, P, i64, P, P, P], i32),
         "cmp_roi_workspace_size": ([IMG, i32], sz),
@@ -268,6 +270,36 @@ class OverComposite(torch.autograd.Function):
                 g = full
             out.append(g.to(l.dtype))
         return (None, None, None, *out)
+
+
+def composite_average(images: Sequence, viewport, out=None, schedule=("seq", 1), tile=(0, 0),
+                      stream=None):
+    """Subpixel compositing (cmp_composite_average): per-channel RGBA8 mean."""
+    x, y, w, h = viewport
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.int32,
+                          device=torch.device("cuda", torch.cuda.current_device()))
+    st = lib().cmp_composite_average(_images(images, "u32"), len(images), _rect(viewport),
+                                     out.data_ptr(), _u32_pitch(out), _schedule(schedule),
+                                     Tile(*tile), _stream(stream))
+    _check(st, "cmp_composite_average")
+    return out
+
+
+def assemble_pixels(images: Sequence, offsets, kernel, viewport, out=None, stream=None):
+    """Pixel-compound assembly (cmp_assemble_pixels); images[i].roi gives the
+    source image size, offsets[i] = (ox, oy) its class in the kernel."""
+    x, y, w, h = viewport
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.int32,
+                          device=torch.device("cuda", torch.cuda.current_device()))
+    n = len(images)
+    offs = (ctypes.c_int32 * max(2, 2 * n))(*[int(v) for o in offsets for v in o])
+    st = lib().cmp_assemble_pixels(_images(images, "u32"), n, offs, int(kernel[0]),
+                                   int(kernel[1]), _rect(viewport), out.data_ptr(),
+                                   _u32_pitch(out), _stream(stream))
+    _check(st, "cmp_assemble_pixels")
+    return out
 
 
 # -------------------------------------------------------------------- ROI

@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kThreads) void rle_clear_kernel(uint64_t* p, int64_
     p[i] = 0;
 }
 
-__global__ __launch_bounds__(kThreads) void rle_compress_kernel(const RleCArgs a) {
+__global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t stage[kStage];
   __shared__ uint64_t sh[8];
   __shared__ uint32_t s_excl;
@@ -474,7 +474,6 @@ static_assert(sizeof(RleDArgs) <= 4096, "kernel arguments must fit in 4 KiB");
 __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t stage[kStage];
   __shared__ uint16_t ends[kBlock / 2];
-  __shared__ __attribute__((aligned(16))) uint8_t plane_buf[kBlock];
   __shared__ uint64_t sh[8];
   __shared__ uint32_t s_size[8];
   __shared__ uint32_t s_boff, s_next;
@@ -658,18 +657,23 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
         }
         int tok = lo;
         int e = ends[tok];
-        uint8_t v = stage[off + 2 * tok + 1];
+        uint64_t v = stage[off + 2 * tok + 1];
         const int last = min(q0 + kPxPerLane, len);
+        uint64_t b_lo = 0, b_hi = 0;   // the lane's 16 bytes, filled in order
         for (int pos = q0; pos < last; ++pos) {
           while (pos >= e && tok + 1 < ntok) {
             ++tok;
             e = ends[tok];
             v = stage[off + 2 * tok + 1];
           }
-          plane_buf[pos] = v;
+          const int j = pos - q0;
+          if (j < 8) b_lo |= v << (8 * j);
+          else b_hi |= v << (8 * (j - 8));
         }
+        pb = u32x4{(uint32_t)b_lo, (uint32_t)(b_lo >> 32), (uint32_t)b_hi, (uint32_t)(b_hi >> 32)};
+      } else {
+        pb = u32x4{0, 0, 0, 0};
       }
-      pb = reinterpret_cast<const u32x4*>(plane_buf)[tid];   // own bytes only: no barrier
       __syncthreads();   // ends[] is rewritten by the next plane
     }
 #pragma unroll

@@ -587,3 +587,58 @@ def test_rle_swizzled_streams():
     assert (st == 0).all()
     for im, o, (x, y, w, h) in zip(imgs, outs, rois):
         assert torch.equal(o.color[:h, :w], im.color[y:y + h, x:x + w])
+
+
+# ------------------------------------------------------ subpixel / pixel
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 16, 64])
+def test_composite_average(n):
+    """Subpixel compositing: 4 x 640x480 style samples, partial placements,
+    every schedule and tile bit-identical to the oracle."""
+    rng = np.random.default_rng(500 + n)
+    W, H = 333, 201
+    imgs = []
+    for i in range(n):
+        full = i % 3 != 2
+        w, h = (W, H) if full else (int(rng.integers(1, W)), int(rng.integers(1, H)))
+        x, y = (0, 0) if full else (int(rng.integers(-5, W)), int(rng.integers(-5, H)))
+        P = w + int(rng.integers(0, 4))
+        c = rng.integers(0, 2 ** 32, (h, P), dtype=np.uint64).astype(np.uint32)
+        imgs.append(cmp.Image(torch.from_numpy(c.view(np.int32)).to(DEV), None, (x, y, w, h)))
+    vp = (2, 3, W, H)
+    note(f"average n={n}")
+    ref = oracle.composite_average([u32(i.color) for i in imgs], [i.roi for i in imgs], vp)
+    for sched, tile in [(("seq", 1), (0, 0)), (("direct_send", 5), (64, 8)),
+                        (("binary_swap", 16), (128, 4)), (("seq", 1), (50, 3))]:
+        out = cmp.composite_average(imgs, vp, schedule=sched, tile=tile)
+        torch.cuda.synchronize()
+        assert (u32(out) == ref).all(), (sched, tile)
+
+
+@pytest.mark.parametrize("kx,ky", [(2, 2), (3, 2), (1, 4), (8, 8), (4, 1)])
+def test_assemble_pixels(kx, ky):
+    rng = np.random.default_rng(kx * 31 + ky)
+    W, H = 517, 203
+    img = rng.integers(0, 2 ** 32, (H, W), dtype=np.uint64).astype(np.uint32)
+    imgs, offs = [], []
+    classes = [(ox, oy) for oy in range(ky) for ox in range(kx)]
+    rng.shuffle(classes)
+    drop = classes[-1] if len(classes) > 2 else None
+    for (ox, oy) in classes:
+        if (ox, oy) == drop:
+            continue      # one class without a source stays 0
+        part = np.ascontiguousarray(img[oy::ky, ox::kx])
+        P = part.shape[1] + 3
+        buf = np.zeros((part.shape[0], P), np.uint32)
+        buf[:, :part.shape[1]] = part
+        imgs.append(cmp.Image(torch.from_numpy(buf.view(np.int32)).to(DEV), None,
+                              (0, 0, part.shape[1], part.shape[0])))
+        offs.append((ox, oy))
+    note(f"assemble {kx}x{ky}")
+    out = cmp.assemble_pixels(imgs, offs, (kx, ky), (0, 0, W, H))
+    torch.cuda.synchronize()
+    ref = oracle.assemble_pixels([u32(i.color) for i in imgs], offs, (kx, ky), (0, 0, W, H))
+    assert (u32(out) == ref).all()
+    exp = img.copy()
+    if drop is not None:
+        exp[drop[1]::ky, drop[0]::kx] = 0
+    assert (ref == exp).all()
