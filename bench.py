@@ -163,6 +163,32 @@ def time_graph(frames, steps, s_obj):
     return t0.elapsed_time(t1)
 
 
+def bandwidth_probe(dev, nbytes=2 << 30, reps=10):
+    """Measured streaming bandwidth (read-only and copy) of a buffer far
+    larger than the Infinity Cache: the practical ceiling next to the spec."""
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    L = cmp.lib()
+    s = torch.cuda.current_stream().cuda_stream
+    res = {}
+    for mode, name, moved in [(0, "read_GBps", nbytes), (1, "copy_GBps", 2 * nbytes)]:
+        for _ in range(2):
+            L.cmp_bandwidth_probe(mode, src.data_ptr(), dst.data_ptr(), nbytes, s)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            st = L.cmp_bandwidth_probe(mode, src.data_ptr(), dst.data_ptr(), nbytes, s)
+            if st != 0:
+                raise cmp.CmpError(st, "cmp_bandwidth_probe", L.cmp_last_error().decode())
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = moved / (e0.elapsed_time(e1) / reps) / 1e6
+    del src, dst
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(frame_host, budget_s=25.0):
     """The oracle chain of one full frame on the host (single thread)."""
     import oracle
@@ -364,6 +390,7 @@ def main():
                         "GBps": float(abytes[name] / stage_ms[k] / 1e6)}
     dom = max(STAGES, key=lambda n: stages[n]["us"])
     graph_ms = time_graph(frames, args.steps, s_obj) / args.steps
+    probe = bandwidth_probe(dev)
     step_bytes = sum(abytes.values())
     achieved = stages[dom]["GBps"]
     traffic = None
@@ -399,6 +426,7 @@ def main():
         "stages": stages,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS, "traffic": traffic},
+        "probe": dict(probe, frac_of_read_probe=achieved / probe["read_GBps"]),
         "wall_s_timed": wall,
     }
     if not args.no_extras:

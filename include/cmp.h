@@ -340,6 +340,15 @@ void       cmp_batch_plan_destroy(cmp_batch_plan* plan);
 cmp_status cmp_autotune(const cmp_job* jobs, int32_t njobs, const char* cache_path, int32_t reps,
                         void* stream);
 
+/*
+ * Bandwidth probes (measurement helpers, not part of the method): mode 0
+ * reads `bytes` from src with 16-byte loads (dst: device, at least 4 bytes,
+ * written only in an (almost) impossible case that keeps the loads alive);
+ * mode 1 copies `bytes` from src to dst. 16-byte aligned, bytes % 16 == 0.
+ */
+cmp_status cmp_bandwidth_probe(int32_t mode, const void* src, void* dst, size_t bytes,
+                               void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
         "cmp_batch_run_plain": ([P, P], i32),
         "cmp_batch_info": ([P, ctypes.POINTER(i64), ctypes.POINTER(i32)], i32),
         "cmp_batch_plan_destroy": ([P], None),
+        "cmp_bandwidth_probe": ([i32, P, P, sz, P], i32),
         "cmp_autotune": ([ctypes.POINTER(CJob), i32, ctypes.c_char_p, i32, P], i32),
     }
     for name, (args, res) in sig.items():
