@@ -222,6 +222,19 @@ cmp_status cmp_roi_detect(const cmp_image* imgs, int32_t n, cmp_format fmt, int3
                           void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * ROI with holes: the occupancy of cell_w x cell_h cells (Section 5.3: the
+ * framebuffer analysis can also detect holes in the rendered area). A cell
+ * is 1 when any of its pixels holds data (the same test as cmp_roi_detect),
+ * else 0; the last row and column of cells may be smaller. The grids of the
+ * n images lie back to back in grid_dev (device bytes): image i's grid has
+ * gh_i = ceil(h_i / cell_h) rows of gw_i = ceil(w_i / cell_w) bytes and
+ * starts after the grids of images 0..i-1. n <= 64.
+ * Errors: CMP_EINVAL, CMP_EHIP.
+ */
+cmp_status cmp_roi_grid(const cmp_image* imgs, int32_t n, cmp_format fmt, int32_t cell_w,
+                        int32_t cell_h, uint8_t* grid_dev, void* stream);
+
+/*
  * Per-component run-length encoding (Section 5.5.1, Enhanced RLE Compression:
  * one RLE stream per component of the pixel, and the image decomposed into
  * sub-images that are compressed in parallel). Stream format "RLE1"; all

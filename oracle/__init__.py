@@ -89,6 +89,8 @@ def lib():
         L.orc_composite_average_rgba8.restype = None
         L.orc_assemble_pixels.argtypes = [i32, P, P, P, P, i32, i32, Rect, P, i64]
         L.orc_assemble_pixels.restype = None
+        L.orc_roi_grid.argtypes = [i32, P, i32, i32, i64, i32, i32, P]
+        L.orc_roi_grid.restype = None
         _lib = L
     return _lib
 
@@ -332,3 +334,20 @@ def assemble_pixels(colors, offsets, kernel, viewport):
                               int(kernel[0]), int(kernel[1]), Rect(*viewport), _ptr(out),
                               viewport[2])
     return out
+
+
+def roi_grid(image, cell, mode="depth", w=None, h=None):
+    """Occupancy of cw x ch cells (Section 5.3, holes in the ROI): uint8
+    array (ceil(h / ch), ceil(w / cw)). mode: "depth", "rgba8" or "float"."""
+    cw, ch = cell
+    if mode == "float":
+        a = np.ascontiguousarray(np.asarray(image).astype(np.float64))
+        m = 2
+    else:
+        a = _contig(image, np.uint32)
+        m = 0 if mode == "depth" else 1
+    h = a.shape[0] if h is None else h
+    w = a.shape[1] if w is None else w
+    g = np.zeros(((h + ch - 1) // ch, (w + cw - 1) // cw), np.uint8)
+    lib().orc_roi_grid(m, _ptr(a), w, h, a.shape[1], cw, ch, _ptr(g))
+    return g

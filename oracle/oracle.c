@@ -640,3 +640,30 @@ void orc_assemble_pixels(int32_t n, const uint32_t* const* color, const int64_t*
         }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* ROI with holes (Section 5.3: analysing the framebuffer also detects      */
+/* holes in the rendered area). Reading: the image is cut into cells of     */
+/* cw x ch pixels (the last row and column of cells may be smaller); a      */
+/* cell is occupied (1) when any of its pixels holds data under the same    */
+/* emptiness test as the bounding box, else 0. `mode`: 0 depth != clear,    */
+/* 1 RGBA8 word != 0, 2 float RGBA (passed as double) any channel != 0.     */
+/* grid: gh x gw bytes, row-major, gw = ceil(w / cw), gh = ceil(h / ch).    */
+/* ------------------------------------------------------------------------ */
+void orc_roi_grid(int32_t mode, const void* data, int32_t w, int32_t h, int64_t pitch,
+                  int32_t cw, int32_t ch, uint8_t* grid)
+{
+    const int64_t gw = (w + cw - 1) / cw, gh = (h + ch - 1) / ch;
+    for (int64_t i = 0; i < gw * gh; ++i) grid[i] = 0;
+    for (int64_t y = 0; y < h; ++y)
+        for (int64_t x = 0; x < w; ++x) {
+            int full = 0;
+            if (mode == 0) full = ((const uint32_t*)data)[y * pitch + x] != ORC_CLEAR_DEPTH;
+            else if (mode == 1) full = ((const uint32_t*)data)[y * pitch + x] != 0u;
+            else {
+                const double* p = (const double*)data + 4 * (y * pitch + x);
+                full = p[0] != 0.0 || p[1] != 0.0 || p[2] != 0.0 || p[3] != 0.0;
+            }
+            if (full) grid[(y / ch) * gw + (x / cw)] = 1;
+        }
+}

@@ -89,6 +89,7 @@ def lib() -> ctypes.CDLL:
         "cmp_composite_over_backward": ([IMG, i32, i32, P, Rect, P, i64, P, P, P], i32),
         "cmp_roi_workspace_size": ([IMG, i32], sz),
         "cmp_roi_detect": ([IMG, i32, i32, P, P, sz, P], i32),
+        "cmp_roi_grid": ([IMG, i32, i32, i32, i32, P, P], i32),
         "cmp_rle_max_size": ([i32, i32, i32], sz),
         "cmp_rle_workspace_size": ([IMG, i32], sz),
         "cmp_rle_compress": ([IMG, i32, i32, ctypes.c_uint32, P, P, P, P, P, P, sz, P], i32),
@@ -333,6 +334,24 @@ def roi_detect(images: Sequence, fmt: int = RGBA8, roi_out=None, ws=None, stream
                               _stream(stream))
     _check(st, "cmp_roi_detect")
     return roi_out
+
+
+def roi_grid(images: Sequence, cell, fmt: int = RGBA8, stream=None):
+    """Cell occupancy of each image (cmp_roi_grid): a list of uint8 device
+    tensors (ceil(h / ch), ceil(w / cw))."""
+    cw, ch = cell
+    dims = [((int(im.roi[3]) + ch - 1) // ch, (int(im.roi[2]) + cw - 1) // cw) for im in images]
+    total = sum(a * b for a, b in dims)
+    buf = torch.zeros(max(1, total), dtype=torch.uint8,
+                      device=torch.device("cuda", torch.cuda.current_device()))
+    st = lib().cmp_roi_grid(_images(images, "rgba" if fmt != RGBA8 else "u32"), len(images), fmt,
+                            cw, ch, buf.data_ptr(), _stream(stream))
+    _check(st, "cmp_roi_grid")
+    out, o = [], 0
+    for gh, gw in dims:
+        out.append(buf[o:o + gh * gw].view(gh, gw))
+        o += gh * gw
+    return out
 
 
 # -------------------------------------------------------------------- RLE

@@ -189,6 +189,75 @@ static int roi_rows(const cmp_image& I, int bpp) {
 
 static int roi_bpp(cmp_format fmt) { return fmt == CMP_RGBA32F ? 16 : fmt == CMP_RGBA16F ? 8 : 4; }
 
+// ---------------------------------------------------------------- holes
+// Occupancy of cw x ch cells (Section 5.3: analysing the framebuffer also
+// finds holes in the rendered area). A workgroup scans the rows of one cell
+// row and a chunk of whole cells (so each cell has one writer), one pixel
+// per lane per load, kRoiBatch loads in flight; data pixels set their
+// cell's byte flag in LDS, and the flags are written out at the end.
+constexpr int kGridChunkCells = 1024;   // LDS flags per workgroup
+
+struct GridImg {
+  const void* data;
+  int64_t pitch;
+  int32_t w, h;
+  int32_t gw, gh;
+  int32_t chunks;        // cell chunks per cell row
+  int32_t wg_begin;
+  int64_t grid_off;      // byte offset of this image's grid
+};
+
+struct GridArgs {
+  GridImg im[kRoiMax];
+  uint8_t* grid;
+  int32_t n;
+  int32_t cw, ch;
+  int32_t chunk_cells;
+};
+static_assert(sizeof(GridArgs) <= 4096, "kernel arguments must fit in 4 KiB");
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void roi_grid_kernel(const GridArgs a) {
+  constexpr int bpp = MODE == 2 ? 16 : MODE == 3 ? 8 : 4;
+  __shared__ uint8_t flags[kGridChunkCells];
+  const int blk = blockIdx.x;
+  int s = 0;
+  while (s + 1 < a.n && a.im[s + 1].wg_begin <= blk) ++s;
+  const GridImg I = a.im[s];
+  const int local = blk - I.wg_begin;
+  const int band = local / I.chunks, chunk = local - band * I.chunks;
+  const int c0 = chunk * a.chunk_cells;                      // first cell of the chunk
+  const int ncells = min(a.chunk_cells, I.gw - c0);
+  const int x0 = c0 * a.cw, x1 = min(I.w, (c0 + ncells) * a.cw);
+  const int y0 = band * a.ch, y1 = min(I.h, y0 + a.ch);
+  for (int k = threadIdx.x; k < ncells; k += kThreads) flags[k] = 0;
+  __syncthreads();
+  const int cols = x1 - x0;
+  const int work = cols * (y1 - y0);
+  const uint8_t* base = reinterpret_cast<const uint8_t*>(I.data);
+  for (int t0 = threadIdx.x; t0 < work; t0 += kThreads * kRoiBatch) {
+    uint32_t m[kRoiBatch];
+    int xs[kRoiBatch];
+#pragma unroll
+    for (int k = 0; k < kRoiBatch; ++k) {
+      m[k] = 0;
+      xs[k] = 0;
+      const int t = t0 + k * kThreads;
+      if (t < work) {
+        const int ry = t / cols, x = x0 + (t - ry * cols);
+        xs[k] = x;
+        m[k] = px_mask<MODE>(base + (int64_t)(y0 + ry) * I.pitch * bpp, x);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kRoiBatch; ++k)
+      if (m[k]) flags[(xs[k] - x0) / a.cw] = 1;   // every writer stores the same value
+  }
+  __syncthreads();
+  uint8_t* g = a.grid + I.grid_off + (int64_t)band * I.gw + c0;
+  for (int k = threadIdx.x; k < ncells; k += kThreads) g[k] = flags[k];
+}
+
 }  // namespace cmp
 
 using namespace cmp;
@@ -253,6 +322,64 @@ extern "C" cmp_status cmp_roi_detect(const cmp_image* imgs, int32_t n, cmp_forma
     case 1: hipLaunchKernelGGL(roi_kernel<1>, dim3((unsigned)wg), dim3(kThreads), 0, s, a); break;
     case 2: hipLaunchKernelGGL(roi_kernel<2>, dim3((unsigned)wg), dim3(kThreads), 0, s, a); break;
     default: hipLaunchKernelGGL(roi_kernel<3>, dim3((unsigned)wg), dim3(kThreads), 0, s, a); break;
+  }
+  CMP_CHECK_HIP(hipGetLastError());
+  return CMP_OK;
+}
+
+extern "C" cmp_status cmp_roi_grid(const cmp_image* imgs, int32_t n, cmp_format fmt,
+                                   int32_t cell_w, int32_t cell_h, uint8_t* grid_dev,
+                                   void* stream) {
+  CMP_REQUIRE(n >= 0 && n <= kRoiMax, "n = %d must be 0..%d", n, kRoiMax);
+  if (n == 0) return CMP_OK;
+  CMP_REQUIRE(imgs && grid_dev, "NULL argument");
+  CMP_REQUIRE(cell_w >= 1 && cell_h >= 1, "cells must be at least 1x1");
+  CMP_REQUIRE(fmt == CMP_RGBA8 || fmt == CMP_RGBA32F || fmt == CMP_RGBA16F, "bad format %d", fmt);
+  int mode = fmt == CMP_RGBA32F ? 2 : fmt == CMP_RGBA16F ? 3 : 1;
+  if (fmt == CMP_RGBA8) {
+    const bool d0 = imgs[0].depth != nullptr;
+    for (int i = 1; i < n; ++i)
+      CMP_REQUIRE((imgs[i].depth != nullptr) == d0,
+                  "either every image has a depth buffer or none has");
+    mode = d0 ? 0 : 1;
+  }
+  const int bpp = roi_bpp(fmt);
+  GridArgs a;
+  memset(&a, 0, sizeof a);
+  a.cw = cell_w;
+  a.ch = cell_h;
+  a.chunk_cells = kGridChunkCells;
+  if ((int64_t)a.chunk_cells * cell_w > 4096) a.chunk_cells = 4096 / cell_w > 0 ? 4096 / cell_w : 1;
+  int64_t wg = 0, goff = 0;
+  for (int i = 0; i < n; ++i) {
+    const cmp_image& I = imgs[i];
+    CMP_REQUIRE(rect_valid(I.roi), "imgs[%d] has a negative size", i);
+    const bool empty = rect_empty(I.roi);
+    const int W = empty ? 0 : I.roi.w, H = empty ? 0 : I.roi.h;
+    const void* data = mode == 0 ? (const void*)I.depth : I.color;
+    if (!empty) {
+      CMP_REQUIRE(data, "imgs[%d]: NULL buffer", i);
+      CMP_REQUIRE(I.pitch >= W, "imgs[%d].pitch < width", i);
+      CMP_REQUIRE((uintptr_t)data % (uintptr_t)(bpp < 16 ? bpp : 16) == 0,
+                  "imgs[%d]: misaligned buffer", i);
+    }
+    const int gw = (W + cell_w - 1) / cell_w, gh = (H + cell_h - 1) / cell_h;
+    const int chunks = (gw + a.chunk_cells - 1) / a.chunk_cells;
+    a.im[i] = GridImg{data, I.pitch, W, H, gw, gh, chunks, (int32_t)wg, goff};
+    wg += (int64_t)gh * chunks;
+    goff += (int64_t)gw * gh;
+  }
+  CMP_REQUIRE(wg < (1 << 24), "too many workgroups");
+  if (wg == 0) return CMP_OK;
+  a.grid = grid_dev;
+  a.n = n;
+  hipStream_t s = (hipStream_t)stream;
+  const dim3 grid((unsigned)wg), block(kThreads);
+  switch (mode) {
+    case 0: hipLaunchKernelGGL(roi_grid_kernel<0>, grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL(roi_grid_kernel<1>, grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(roi_grid_kernel<2>, grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL(roi_grid_kernel<3>, grid, block, 0, s, a); break;
   }
   CMP_CHECK_HIP(hipGetLastError());
   return CMP_OK;

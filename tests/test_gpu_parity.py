@@ -642,3 +642,35 @@ def test_assemble_pixels(kx, ky):
     if drop is not None:
         exp[drop[1]::ky, drop[0]::kx] = 0
     assert (ref == exp).all()
+
+
+@pytest.mark.parametrize("fmt,cell", [("depth", (64, 64)), ("depth", (7, 5)), ("rgba8", (16, 16)),
+                                      ("f32", (32, 8)), ("f16", (3, 3)), ("depth", (5000, 2))])
+def test_roi_grid_holes(fmt, cell):
+    rng = np.random.default_rng(len(fmt) * 100 + cell[0])
+    imgs, refs = [], []
+    for k, (h, w) in enumerate([(130, 257), (64, 64), (1, 1), (211, 333)]):
+        P = w + (k % 2) * 4
+        m = np.zeros((h, P), bool)
+        for _ in range(4):   # a few blobs leave holes between them
+            y, x = rng.integers(0, h), rng.integers(0, w)
+            m[y:y + 9, x:x + 13] = True
+        m[:, w:] = False
+        if fmt in ("depth", "rgba8"):
+            a = np.where(m, rng.integers(1, F - 1, (h, P), dtype=np.uint64), F if fmt == "depth" else 0).astype(np.uint32)
+            t = torch.from_numpy(a.view(np.int32)).to(DEV)
+            imgs.append(cmp.Image(t, t if fmt == "depth" else None, (0, 0, w, h)))
+            refs.append(oracle.roi_grid(a, cell, mode=fmt, w=w, h=h))
+        else:
+            L = np.zeros((h, P, 4), np.float32)
+            L[m, 2] = 0.75
+            L[~m, 0] = -0.0
+            L = L.astype(np.float16 if fmt == "f16" else np.float32)
+            imgs.append(cmp.Image(torch.from_numpy(L).to(DEV), None, (0, 0, w, h)))
+            refs.append(oracle.roi_grid(L, cell, mode="float", w=w, h=h))
+    note(f"roi grid {fmt} {cell}")
+    f = {"depth": cmp.RGBA8, "rgba8": cmp.RGBA8, "f32": cmp.RGBA32F, "f16": cmp.RGBA16F}[fmt]
+    grids = cmp.roi_grid(imgs, cell, fmt=f)
+    torch.cuda.synchronize()
+    for g, r in zip(grids, refs):
+        assert (g.cpu().numpy() == r).all()

@@ -341,3 +341,40 @@ def test_swizzle_round_trip_and_gain_on_shaded_colour():
     s = oracle.rle_compress(noise, noise, (1, 2, 50, 30), swizzle=True)
     _, c3, d3 = oracle.rle_decompress(s)
     assert (c3 == noise[2:32, 1:51]).all() and (d3 == noise[2:32, 1:51]).all()
+
+
+# ------------------------------------------------------- ROI with holes
+def test_roi_grid_hand_worked():
+    """A 6x5 depth image, 2x2 cells: data at (0,0), (5,1) and (2,4); the
+    occupancy is worked out by hand; the hole in the middle stays 0."""
+    d = np.full((5, 6), F, np.uint32)
+    d[0, 0] = 1
+    d[1, 5] = 7
+    d[4, 2] = 3
+    g = oracle.roi_grid(d, (2, 2))
+    assert g.tolist() == [[1, 0, 1], [0, 0, 0], [0, 1, 0]]
+    assert oracle.roi_grid(np.full((5, 6), F, np.uint32), (4, 3)).tolist() == [[0, 0], [0, 0]]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_roi_grid_brute_force(seed):
+    rng = np.random.default_rng(900 + seed)
+    H, W = int(rng.integers(1, 70)), int(rng.integers(1, 90))
+    cw, ch = int(rng.integers(1, 17)), int(rng.integers(1, 17))
+    m = rng.random((H, W)) < 0.01
+    d = np.where(m, 5, F).astype(np.uint32)
+    g = oracle.roi_grid(d, (cw, ch))
+    for cy in range(g.shape[0]):
+        for cx in range(g.shape[1]):
+            assert g[cy, cx] == int(m[cy * ch:(cy + 1) * ch, cx * cw:(cx + 1) * cw].any())
+    # the bounding box of the occupied cells contains the ROI
+    x, y, w, h = oracle.roi_detect_depth(d)
+    if w:
+        ys, xs = np.nonzero(g)
+        assert xs.min() * cw <= x and (xs.max() + 1) * cw >= x + w
+        assert ys.min() * ch <= y and (ys.max() + 1) * ch >= y + h
+    # float layers: -0.0 is empty, NaN is data
+    f = np.zeros((H, W, 4), np.float32)
+    f[m, 1] = 0.5
+    f[~m, 3] = -0.0
+    assert (oracle.roi_grid(f, (cw, ch), mode="float") == g).all()
