@@ -348,7 +348,8 @@ def main():
     ap.add_argument("--copies", type=int, default=4, help="buffer copies rotated per step")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", default="", help="profile helper: run only this stage repeatedly")
+    ap.add_argument("--only", default="", help="profile helper: run only this stage (or probe_copy, a 1 GiB copy) "
+                    "repeatedly")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
@@ -356,6 +357,20 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.only == "probe_copy":
+        # reference kernel for scaling HBM counters: a 1 GiB copy (1 GiB read + 1 GiB written)
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        L = cmp.lib()
+        for _ in range(args.steps):
+            st = L.cmp_bandwidth_probe(1, src.data_ptr(), dst.data_ptr(), nbytes,
+                                       torch.cuda.current_stream().cuda_stream)
+            if st != 0:
+                raise cmp.CmpError(st, "cmp_bandwidth_probe", L.cmp_last_error().decode())
+        torch.cuda.synchronize()
+        log(f"copied {nbytes} bytes {args.steps} times")
+        return
     log("generating 16 x 1920x1080 contributors")
     frames = []
     for c in range(args.copies):
@@ -394,14 +409,9 @@ def main():
     step_bytes = sum(abytes.values())
     achieved = stages[dom]["GBps"]
     traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tpath):
-        try:
-            t = json.load(open(tpath))
-            if t.get("kernel_stage") == dom and t.get("source_hash") == _source_hash():
-                traffic = t.get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    t = read_traffic(os.path.join(ROOT, "profiles", f"hbm_traffic_{dom}.txt"))
+    if t and t.get("source_hash") == _source_hash():
+        traffic = float(t["bytes_per_launch"])
     result = {
         "metric": METRIC,
         "value": roi_px / (ms_step * 1e3),
@@ -449,6 +459,20 @@ def main():
                                   "sample": f"one full frame (16 x 1920x1080) of the same pipeline, "
                                             f"median of {reps} runs, {t:.2f} s each"}
     print(json.dumps(result), flush=True)
+
+
+def read_traffic(path):
+    """`key: value` lines of a committed HBM-counter summary (None if absent).
+    The counters are only valid for the kernel sources they were taken on,
+    so the summary carries a hash of those sources."""
+    if not os.path.exists(path):
+        return None
+    out = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            out[k.strip()] = v.strip()
+    return out if "bytes_per_launch" in out else None
 
 
 def _source_hash():
