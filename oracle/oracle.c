@@ -534,7 +534,7 @@ int orc_rle_header(const uint8_t* in, uint64_t size, orc_rect* roi, int32_t* npl
 /* Decodes into ROI-sized buffers (w x h, out_pitch). `out_depth` must be    */
 /* given for 8-plane streams. Returns 0, or -1 if the stream is corrupt      */
 /* (bad header, tables that disagree, token runs that do not add up to the  */
-/* block length).                                                           */
+/* block length, a run that crosses a multiple of 256 pixels).              */
 int orc_rle_decompress(const uint8_t* in, uint64_t size, uint32_t* out_color, uint32_t* out_depth,
                        int64_t out_pitch, orc_rect* roi_out)
 {
@@ -558,6 +558,8 @@ int orc_rle_decompress(const uint8_t* in, uint64_t size, uint32_t* out_color, ui
                 for (uint32_t t = 0; t < sz / 2; ++t) {
                     const int64_t run = (int64_t)src[2 * t] + 1;
                     if (j + run > len) return -1;
+                    /* runs end at multiples of 256 pixels at the latest */
+                    if ((j % RLE_SEG) + run > RLE_SEG) return -1;
                     for (int64_t e = 0; e < run; ++e) plane[j + e] = src[2 * t + 1];
                     j += run;
                 }

@@ -25,10 +25,14 @@
 // the ROIs leave out cost nothing.
 //
 // Decompression: a grid-stride loop over the blocks of all streams (counted
-// from the stream headers); per block: header and table checks, payload to
-// LDS, per plane a scan of the run lengths and, per lane, a binary search for
-// its first run; pixels are assembled in registers and written with 16-byte
-// stores.
+// from the stream headers); per block: table checks (uniform loads, every
+// lane checks), payload to LDS, each lane's 16-byte window of every plane
+// (its 16 raw bytes or its 8 tokens), one workgroup scan of the run-length
+// sums of all run-coded planes, each run's value and start bit scattered
+// into LDS, and per lane a fill of its 16 pixels from the last run start.
+// The value entering a lane comes from a scan over its DPP row of 16 lanes:
+// a row covers one 256-pixel segment, which no run crosses. Pixels are
+// assembled in registers and written with 16-byte stores.
 #include <string.h>
 
 #include "cmp_internal.hpp"
@@ -471,13 +475,54 @@ struct RleDArgs {
 };
 static_assert(sizeof(RleDArgs) <= 4096, "kernel arguments must fit in 4 KiB");
 
+// Exclusive workgroup scan of kW packed words; also returns the totals.
+// `sh` holds 4 * kW words; ends with a barrier.
+template <int kW>
+__device__ __forceinline__ void block_scan_n(const uint64_t (&v)[kW], uint64_t (&ex)[kW],
+                                             uint64_t (&tot)[kW], uint64_t* sh) {
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  uint64_t inc[kW];
+#pragma unroll
+  for (int i = 0; i < kW; ++i) {
+    inc[i] = wave_incl_scan(v[i]);
+    if (lane == kWave - 1) sh[4 * i + wave] = inc[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kW; ++i) {
+    uint64_t p = 0, t = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / kWave; ++w) {
+      const uint64_t x = sh[4 * i + w];
+      if (w < wave) p += x;
+      t += x;
+    }
+    ex[i] = p + inc[i] - v[i];
+    tot[i] = t;
+  }
+  __syncthreads();
+}
+
+// Run-length sums of a block's planes, 21-bit fields, three per word: a
+// plane of < 2048 tokens of <= 256 pixels sums to < 2^21, so no field can
+// overflow into the next, whatever the stream holds.
+__device__ __forceinline__ int fld_word(int k) { return k / 3; }
+__device__ __forceinline__ int fld_shift(int k) { return 21 * (k % 3); }
+constexpr uint64_t kFld = (1u << 21) - 1;
+
+// DPP row shift right by D lanes inside rows of 16 lanes; lanes whose source
+// lies outside the row read 0.
+template <int D>
+__device__ __forceinline__ uint32_t row_shr(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x110 + D, 0xF, 0xF, true);
+}
+
 __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs a) {
+  // the block payload, later the bytes of its runs at their start positions
   __shared__ __attribute__((aligned(16))) uint8_t stage[kStage];
-  __shared__ uint16_t ends[kBlock / 2];
-  __shared__ uint64_t sh[8];
-  __shared__ uint32_t s_size[8];
-  __shared__ uint32_t s_boff, s_next;
-  __shared__ int32_t s_err;
+  __shared__ __attribute__((aligned(16))) uint32_t starts[8][kBlock / 32];   // run-start bits
+  __shared__ uint64_t sh[12];
+  __shared__ int32_t s_bad[kThreads / kWave];
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
 
@@ -555,47 +600,47 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
   if ((uint64_t)b >= nb) continue;   // uniform: a stream without blocks
   const int64_t npx = (int64_t)rw * rh;
   const int len = (int)imin64(kBlock, npx - (int64_t)b * kBlock);
+  // block table: uniform addresses, every lane checks the same values
+  // (three loads issued together; all inside the table the header check
+  // found readable, since np is 4 or 8 and entry nb is the first size)
   const uint32_t* tbl = reinterpret_cast<const uint32_t*>(I.in + 32);
-  if (tid < np) s_size[tid] = tbl[nb + (uint64_t)b * np + tid];
-  if (tid == 8) s_boff = tbl[b];
-  if (tid == 9) s_next = (uint64_t)b + 1 < nb ? tbl[b + 1] : 0u;
-  __syncthreads();
-  if (tid == 0) {
-    int e = 0;
-    uint64_t tot = 0;
-    for (int k = 0; k < np; ++k) {
-      const uint32_t sz = s_size[k];
-      if (sz > (uint32_t)len || (sz < (uint32_t)len && (sz == 0 || (sz & 1u)))) e = CMP_ECORRUPT;
-      tot += sz;
-    }
-    const uint32_t boff = s_boff;
-    if ((boff & 15u) || (b == 0 && boff != 0)) e = CMP_ECORRUPT;
-    if ((uint64_t)b + 1 < nb && (uint64_t)s_next != boff + align16(tot)) e = CMP_ECORRUPT;
-    if (rle_p0(nb, np) + boff + align16(tot) > I.in_bytes) e = CMP_ECORRUPT;
-    if (e) a.status[s] = e;
-    s_err = e;
-  }
-  __syncthreads();
-  if (s_err) {
-    __syncthreads();
-    continue;
-  }
+  const uint32_t* srow = tbl + nb + (uint64_t)b * np;
+  const u32x4 s03 = ld_u32x4(srow);
+  const u32x4 s47 = ld_u32x4(srow + (np == 8 ? 4 : 0));
+  const uint2 bo = *reinterpret_cast<const uint2*>(tbl + b);   // 4-byte aligned pair
   uint32_t size[8], poff[8], btotal = 0;
+  int e = 0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    size[k] = k < np ? s_size[k] : 0;
+    size[k] = k < 4 ? s03[k] : np == 8 ? s47[k - 4] : 0u;
+    if (k < np && (size[k] > (uint32_t)len ||
+                   (size[k] < (uint32_t)len && (size[k] == 0 || (size[k] & 1u)))))
+      e = CMP_ECORRUPT;
     poff[k] = btotal;
     btotal += size[k];
   }
+  const uint32_t boff = bo.x;
+  const uint32_t bnext = bo.y;   // the first size entry when b is the last block
+  if ((boff & 15u) || (b == 0 && boff != 0)) e = CMP_ECORRUPT;
+  if ((uint64_t)b + 1 < nb && (uint64_t)bnext != boff + align16(btotal)) e = CMP_ECORRUPT;
+  if (rle_p0(nb, np) + boff + align16(btotal) > I.in_bytes) e = CMP_ECORRUPT;
+  if (e) {   // uniform; no LDS was touched in this slot
+    if (tid == 0) a.status[s] = e;
+    continue;
+  }
+  uint32_t tokmask = 0;   // planes stored as runs
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (k < np && size[k] != (uint32_t)len) tokmask |= 1u << k;
   const uint32_t padded = (uint32_t)align16(btotal);
+  reinterpret_cast<u32x4*>(&starts[0][0])[tid] = u32x4{0, 0, 0, 0};
   {
     // the whole block payload to LDS: all loads in flight before the stores
-    const u32x4* src = reinterpret_cast<const u32x4*>(I.in + rle_p0(nb, np) + s_boff);
+    const u32x4* src = reinterpret_cast<const u32x4*>(I.in + rle_p0(nb, np) + boff);
     u32x4* dst = reinterpret_cast<u32x4*>(stage);
-    const uint32_t nv = padded / 16;
     constexpr int kMaxPer = (8 * kBlock / 16 + kThreads - 1) / kThreads;
     u32x4 tmp[kMaxPer];
-    const int nvi = (int)nv;
+    const int nvi = (int)(padded / 16);
 #pragma unroll
     for (int k = 0; k < kMaxPer; ++k)
       tmp[k] = tid + k * kThreads < nvi ? __builtin_nontemporal_load(&src[tid + k * kThreads]) : u32x4{0, 0, 0, 0};
@@ -605,87 +650,125 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
   }
   __syncthreads();
 
+  // Every plane's 16-byte window of this lane: the raw bytes of its 16
+  // pixels, or its 8 tokens (run length - 1, value). Planes start at even
+  // offsets, so the window is 5 aligned words shifted by 0 or 2 bytes.
   const int q0 = tid * kPxPerLane;
-  uint32_t col[kPxPerLane], dep[kPxPerLane];
+  u32x4 win[8];
 #pragma unroll
-  for (int j = 0; j < kPxPerLane; ++j) { col[j] = 0; dep[j] = 0; }
-  bool bad = false;
-#pragma unroll 1
-  for (int k = 0; k < np; ++k) {
-    const uint32_t off = poff[k];
-    const int sh8 = 8 * (k & 3);
-    u32x4 pb;   // this lane's 16 bytes of plane k
-    if (size[k] == (uint32_t)len) {
-      uint32_t w4[4] = {0, 0, 0, 0};
-      if ((off & 3u) == 0 && q0 + kPxPerLane <= len) {   // aligned: four 32-bit loads
-#pragma unroll
-        for (int v = 0; v < 4; ++v) w4[v] = *reinterpret_cast<const uint32_t*>(stage + off + q0 + 4 * v);
+  for (int k = 0; k < 8; ++k) {
+    win[k] = u32x4{0, 0, 0, 0};
+    if (k < np) {
+      const uint32_t off = poff[k] + (uint32_t)q0;
+      const uint32_t* w = reinterpret_cast<const uint32_t*>(stage) + (off >> 2);
+      const uint32_t d0 = w[0], d1 = w[1], d2 = w[2], d3 = w[3];
+      if (poff[k] & 2u) {
+        const uint32_t d4 = w[4];
+        win[k] = u32x4{__builtin_amdgcn_alignbyte(d1, d0, 2), __builtin_amdgcn_alignbyte(d2, d1, 2),
+                       __builtin_amdgcn_alignbyte(d3, d2, 2), __builtin_amdgcn_alignbyte(d4, d3, 2)};
       } else {
-#pragma unroll
-        for (int j = 0; j < kPxPerLane; ++j)
-          if (q0 + j < len) w4[j >> 2] |= (uint32_t)stage[off + q0 + j] << (8 * (j & 3));
+        win[k] = u32x4{d0, d1, d2, d3};
       }
-      pb = u32x4{w4[0], w4[1], w4[2], w4[3]};
-    } else {
-      // run lengths -> inclusive ends (8 tokens per lane)
-      const int ntok = (int)(size[k] / 2);
-      uint32_t lens[8];
-      uint32_t mysum = 0;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int ti = tid * 8 + t;
-        lens[t] = ti < ntok ? (uint32_t)stage[off + 2 * ti] + 1u : 0u;
-        mysum += lens[t];
-      }
-      uint64_t ex, ex2, tot, tot2;
-      block_scan2(mysum, 0, ex, ex2, tot, tot2, sh);
-      uint32_t run = (uint32_t)ex;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int ti = tid * 8 + t;
-        run += lens[t];
-        if (ti < ntok) ends[ti] = (uint16_t)min(run, 65535u);
-      }
-      if ((uint32_t)tot != (uint32_t)len) bad = true;   // uniform
-      __syncthreads();
-      if (!bad && q0 < len) {
-        // first run that ends after q0, then walk the runs over the lane's bytes
-        int lo = 0, hi = ntok - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if ((int)ends[mid] > q0) hi = mid; else lo = mid + 1;
-        }
-        int tok = lo;
-        int e = ends[tok];
-        uint64_t v = stage[off + 2 * tok + 1];
-        const int last = min(q0 + kPxPerLane, len);
-        uint64_t b_lo = 0, b_hi = 0;   // the lane's 16 bytes, filled in order
-        for (int pos = q0; pos < last; ++pos) {
-          while (pos >= e && tok + 1 < ntok) {
-            ++tok;
-            e = ends[tok];
-            v = stage[off + 2 * tok + 1];
-          }
-          const int j = pos - q0;
-          if (j < 8) b_lo |= v << (8 * j);
-          else b_hi |= v << (8 * (j - 8));
-        }
-        pb = u32x4{(uint32_t)b_lo, (uint32_t)(b_lo >> 32), (uint32_t)b_hi, (uint32_t)(b_hi >> 32)};
-      } else {
-        pb = u32x4{0, 0, 0, 0};
-      }
-      __syncthreads();   // ends[] is rewritten by the next plane
-    }
-#pragma unroll
-    for (int j = 0; j < kPxPerLane; ++j) {
-      const uint32_t wv = (j < 4 ? pb.x : j < 8 ? pb.y : j < 12 ? pb.z : pb.w);
-      const uint32_t v = (wv >> (8 * (j & 3))) & 0xFFu;
-      if (k < 4) col[j] |= v << sh8; else dep[j] |= v << sh8;
     }
   }
-  if (bad) {
-    if (tid == 0) a.status[s] = CMP_ECORRUPT;
+  bool bad = false;
+  if (tokmask) {   // uniform
+    // start position of this lane's first token in every run-coded plane
+    uint64_t v3[3] = {0, 0, 0}, ex3[3], tot3[3];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (tokmask & (1u << k)) {
+        const int ntok = (int)(size[k] / 2);
+        const uint32_t wv[4] = {win[k].x, win[k].y, win[k].z, win[k].w};
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (tid * 8 + j < ntok) sum += ((wv[j >> 1] >> (16 * (j & 1))) & 0xFFu) + 1u;
+        v3[fld_word(k)] |= (uint64_t)sum << fld_shift(k);
+      }
+    }
+    block_scan_n<3>(v3, ex3, tot3, sh);   // also: every window has been read
+    bool sums_ok = true;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if ((tokmask & (1u << k)) && ((tot3[fld_word(k)] >> fld_shift(k)) & kFld) != (uint64_t)len)
+        sums_ok = false;
+    if (!sums_ok) {   // uniform; the last LDS access of this slot was the scan
+      if (tid == 0) a.status[s] = CMP_ECORRUPT;
+      continue;
+    }
+    // each run's value at its start position, and its start bit
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (tokmask & (1u << k)) {
+        const int ntok = (int)(size[k] / 2);
+        const uint32_t wv[4] = {win[k].x, win[k].y, win[k].z, win[k].w};
+        uint32_t pos = (uint32_t)((ex3[fld_word(k)] >> fld_shift(k)) & kFld);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          if (tid * 8 + j < ntok) {
+            const uint32_t t = wv[j >> 1] >> (16 * (j & 1));
+            stage[k * kBlock + pos] = (uint8_t)(t >> 8);
+            __hip_atomic_fetch_or(&starts[k][pos >> 5], 1u << (pos & 31), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+            pos += (t & 0xFFu) + 1u;
+          }
+        }
+      }
+    }
     __syncthreads();
+    // Expand: a pixel takes the value of the last run start at or before it.
+    // Runs never cross a multiple of 256 pixels, so a 256-pixel segment (the
+    // 16 lanes of one DPP row) starts a run, and the value entering a lane
+    // comes from a scan over its row.
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (tokmask & (1u << k)) {
+        const u32x4 d = *reinterpret_cast<const u32x4*>(stage + k * kBlock + q0);
+        const uint32_t m = (starts[k][q0 >> 5] >> (q0 & 31)) & 0xFFFFu;
+        const uint32_t dv[4] = {d.x, d.y, d.z, d.w};
+        const int hb = 31 - __builtin_clz(m | 1u);
+        const uint32_t hw = hb < 4 ? d.x : hb < 8 ? d.y : hb < 12 ? d.z : d.w;
+        const uint32_t last = (hw >> (8 * (hb & 3))) & 0xFFu;
+        uint32_t x = m ? (0x100u | last) : 0u;
+        uint32_t y;
+        y = row_shr<1>(x); if (!(x & 0x100u)) x = y;
+        y = row_shr<2>(x); if (!(x & 0x100u)) x = y;
+        y = row_shr<4>(x); if (!(x & 0x100u)) x = y;
+        y = row_shr<8>(x); if (!(x & 0x100u)) x = y;
+        uint32_t cur = row_shr<1>(x) & 0xFFu;
+        if ((tid & 15) == 0 && q0 < len && !(m & 1u)) bad = true;   // a run crosses a segment
+        uint32_t o[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < kPxPerLane; ++j) {
+          if (m & (1u << j)) cur = (dv[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+          o[j >> 2] |= cur << (8 * (j & 3));
+        }
+        win[k] = u32x4{o[0], o[1], o[2], o[3]};
+      }
+    }
+  }
+  uint32_t col[kPxPerLane], dep[kPxPerLane];
+#pragma unroll
+  for (int j = 0; j < kPxPerLane; ++j) {
+    const int sh8 = 8 * (j & 3);
+    const int wj = j >> 2;
+    uint32_t c = 0, dd = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      c |= ((win[k][wj] >> sh8) & 0xFFu) << (8 * k);
+      dd |= ((win[k + 4][wj] >> sh8) & 0xFFu) << (8 * k);
+    }
+    col[j] = c;
+    dep[j] = dd;
+  }
+  // a malformed stream must not be written: one vote per wave, then a
+  // barrier that also ends every LDS access of this slot
+  const uint64_t vote = __ballot(bad);
+  if (lane == 0) s_bad[tid / kWave] = vote != 0;
+  __syncthreads();
+  if (s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3]) {
+    if (tid == 0) a.status[s] = CMP_ECORRUPT;
     continue;
   }
   if (swizzled) {
@@ -719,7 +802,6 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
       }
     }
   }
-  __syncthreads();   // LDS is reused by the next slot
   }
 }
 

@@ -94,38 +94,64 @@ __global__ __launch_bounds__(kThreads) void roi_kernel(const RoiArgs a) {
   const int tail = I.w - full_units * ppu;   // pixels handled one by one
 
   int minx = 0x7FFFFFFF, miny = 0x7FFFFFFF, maxx = -1, maxy = -1;
-  const int per_row = full_units + tail;
-  const int work = per_row * (y1 - y0);
-  // lane t takes units t, t + 256, ...; (row, unit) advance incrementally and
-  // kRoiBatch loads are issued before any of them is examined
-  int ry = per_row ? threadIdx.x / per_row : 0;
-  int u = threadIdx.x - ry * per_row;
-  for (int t0 = threadIdx.x; t0 < work; t0 += kThreads * kRoiBatch) {
+  const int nrows = y1 - y0;
+  // Full 16-byte units, flat over (row, unit): lane t takes units t, t + 256,
+  // ...; kRoiBatch loads are issued unconditionally (an index past the end
+  // reads unit 0 of the band instead and is ignored) so they are all in
+  // flight before the first is examined.
+  const int uwork = full_units * nrows;
+  if (uwork > 0) {
+    const int dq = kThreads / full_units, dr = kThreads - dq * full_units;
+    int ry = (int)threadIdx.x / full_units;
+    int u = (int)threadIdx.x - ry * full_units;
+    for (int t0 = threadIdx.x; t0 < uwork; t0 += kThreads * kRoiBatch) {
+      u32x4 v[kRoiBatch];
+      int xs[kRoiBatch], ys[kRoiBatch];
+#pragma unroll
+      for (int k = 0; k < kRoiBatch; ++k) {
+        const bool ok = t0 + k * kThreads < uwork;
+        xs[k] = ok ? u * ppu : -1;
+        ys[k] = y0 + ry;
+        const u32x4* row = reinterpret_cast<const u32x4*>(base + (int64_t)(y0 + (ok ? ry : 0)) * row_bytes);
+        v[k] = row[ok ? u : 0];
+        u += dr;
+        ry += dq;
+        if (u >= full_units) { u -= full_units; ++ry; }
+      }
+#pragma unroll
+      for (int k = 0; k < kRoiBatch; ++k) {
+        const uint32_t m = xs[k] >= 0 ? unit_mask<MODE>(v[k]) : 0u;
+        if (m) {
+          minx = min(minx, xs[k] + (int)__builtin_ctz(m));
+          maxx = max(maxx, xs[k] + 31 - (int)__builtin_clz(m));
+          miny = min(miny, ys[k]);
+          maxy = max(maxy, ys[k]);
+        }
+      }
+    }
+  }
+  // The remaining pixels of each row (all of them when rows are not 16-byte
+  // aligned), one load per pixel, batched the same way.
+  const int twork = tail * nrows;
+  for (int t0 = threadIdx.x; t0 < twork; t0 += kThreads * kRoiBatch) {
     uint32_t m[kRoiBatch];
     int xs[kRoiBatch], ys[kRoiBatch];
 #pragma unroll
     for (int k = 0; k < kRoiBatch; ++k) {
-      m[k] = 0;
-      xs[k] = 0;
-      ys[k] = y0 + ry;
-      if (t0 + k * kThreads < work) {
-        const uint8_t* row = base + (int64_t)(y0 + ry) * row_bytes;
-        if (u < full_units) {
-          m[k] = unit_mask<MODE>(reinterpret_cast<const u32x4*>(row)[u]);
-          xs[k] = u * ppu;
-        } else {
-          xs[k] = full_units * ppu + (u - full_units);
-          m[k] = px_mask<MODE>(row, xs[k]);
-        }
-      }
-      u += kThreads;
-      while (u >= per_row && per_row > 0) { u -= per_row; ++ry; }
+      const int t = t0 + k * kThreads;
+      const bool ok = t < twork;
+      const int tc = ok ? t : 0;
+      const int r = tc / tail;
+      xs[k] = full_units * ppu + (tc - r * tail);
+      ys[k] = y0 + r;
+      const uint32_t mm = px_mask<MODE>(base + (int64_t)(y0 + r) * row_bytes, xs[k]);
+      m[k] = ok ? mm : 0u;
     }
 #pragma unroll
     for (int k = 0; k < kRoiBatch; ++k) {
       if (m[k]) {
-        minx = min(minx, xs[k] + (int)__builtin_ctz(m[k]));
-        maxx = max(maxx, xs[k] + 31 - (int)__builtin_clz(m[k]));
+        minx = min(minx, xs[k]);
+        maxx = max(maxx, xs[k]);
         miny = min(miny, ys[k]);
         maxy = max(maxy, ys[k]);
       }
@@ -240,14 +266,15 @@ __global__ __launch_bounds__(kThreads) void roi_grid_kernel(const GridArgs a) {
     int xs[kRoiBatch];
 #pragma unroll
     for (int k = 0; k < kRoiBatch; ++k) {
-      m[k] = 0;
-      xs[k] = 0;
+      // unconditional load (an index past the end reads the first pixel of
+      // the chunk and is ignored), so that the batch is in flight together
       const int t = t0 + k * kThreads;
-      if (t < work) {
-        const int ry = t / cols, x = x0 + (t - ry * cols);
-        xs[k] = x;
-        m[k] = px_mask<MODE>(base + (int64_t)(y0 + ry) * I.pitch * bpp, x);
-      }
+      const bool ok = t < work;
+      const int tc = ok ? t : 0;
+      const int ry = tc / cols, x = x0 + (tc - ry * cols);
+      xs[k] = x;
+      const uint32_t mm = px_mask<MODE>(base + (int64_t)(y0 + ry) * I.pitch * bpp, x);
+      m[k] = ok ? mm : 0u;
     }
 #pragma unroll
     for (int k = 0; k < kRoiBatch; ++k)

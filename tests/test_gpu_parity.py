@@ -294,6 +294,28 @@ def test_rle_decompress_rejects_corrupt_streams():
     assert (u32(outs[names.index("good")].color) == color).all()
 
 
+def test_rle_decompress_rejects_runs_across_segments():
+    """A run that crosses a multiple of 256 pixels is malformed (the oracle
+    rejects it too); the unmodified stream decodes."""
+    color = np.full((1, 300), 0x7E7E7E7E, np.uint32)
+    good = oracle.rle_compress(color, color.copy(), (0, 0, 300, 1))
+    bad1, bad2 = good.copy(), good.copy()
+    bad1[80], bad1[82] = 199, 99
+    bad2[84], bad2[86] = 254, 44          # plane 1
+    for b in (bad1, bad2):
+        with pytest.raises(oracle.CorruptStream):
+            oracle.rle_decompress(b)
+    streams = [torch.from_numpy(x).to(DEV) for x in (good, bad1, bad2)]
+    outs = [cmp.Image(torch.zeros((1, 300), dtype=torch.int32, device=DEV),
+                      torch.zeros((1, 300), dtype=torch.int32, device=DEV), (0, 0, 300, 1))
+            for _ in streams]
+    note("rle run across segment")
+    _, st = cmp.rle_decompress(streams, outs)
+    torch.cuda.synchronize()
+    assert st.cpu().tolist() == [0, cmp.CMP_ECORRUPT, cmp.CMP_ECORRUPT]
+    assert (u32(outs[0].color) == color).all() and (u32(outs[0].depth) == color).all()
+
+
 # ------------------------------------------------------------------- over
 def _over_layers(rng, n, W, H, dtype, full=False):
     layers = []

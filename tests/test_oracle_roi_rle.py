@@ -265,6 +265,24 @@ def test_corrupt_streams_are_rejected():
         oracle.rle_decompress(good[:20])
 
 
+def test_run_across_segment_is_rejected():
+    """Runs end at multiples of 256 pixels at the latest (the RLE1 format):
+    the 300-pixel constant row is 256 + 44 per plane; moving the split to
+    200 + 100 keeps the sum but makes the second run cross pixel 256."""
+    color = np.full((1, 300), 0x7E7E7E7E, np.uint32)
+    good = oracle.rle_compress(color, color.copy(), (0, 0, 300, 1))
+    assert good[80] == 0xFF and good[82] == 43        # plane 0: (255, v), (43, v)
+    oracle.rle_decompress(good)
+    s = good.copy()
+    s[80], s[82] = 199, 99
+    with pytest.raises(oracle.CorruptStream):
+        oracle.rle_decompress(s)
+    s = good.copy()
+    s[80], s[82] = 254, 44                            # 255 + 45: ends at 300, crosses 256
+    with pytest.raises(oracle.CorruptStream):
+        oracle.rle_decompress(s)
+
+
 def test_max_size_formula():
     for w, h, npl in [(0, 0, 8), (1, 1, 8), (4096, 1, 4), (4097, 1, 8), (1920, 1080, 8)]:
         nb = -(-w * h // 4096)
