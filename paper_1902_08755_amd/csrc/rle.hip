@@ -607,7 +607,8 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
   const uint32_t* srow = tbl + nb + (uint64_t)b * np;
   const u32x4 s03 = ld_u32x4(srow);
   const u32x4 s47 = ld_u32x4(srow + (np == 8 ? 4 : 0));
-  const uint2 bo = *reinterpret_cast<const uint2*>(tbl + b);   // 4-byte aligned pair
+  uint2 bo;   // boff[b], boff[b + 1]: a 4-byte aligned pair
+  __builtin_memcpy(&bo, __builtin_assume_aligned(tbl + b, 4), 8);
   uint32_t size[8], poff[8], btotal = 0;
   int e = 0;
 #pragma unroll
@@ -651,8 +652,9 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
   __syncthreads();
 
   // Every plane's 16-byte window of this lane: the raw bytes of its 16
-  // pixels, or its 8 tokens (run length - 1, value). Planes start at even
-  // offsets, so the window is 5 aligned words shifted by 0 or 2 bytes.
+  // pixels, or its 8 tokens (run length - 1, value). A plane starts at any
+  // byte offset (a raw plane of odd length moves the next one), so the
+  // window is 5 aligned words funnel-shifted by 0..3 bytes.
   const int q0 = tid * kPxPerLane;
   u32x4 win[8];
 #pragma unroll
@@ -661,14 +663,10 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
     if (k < np) {
       const uint32_t off = poff[k] + (uint32_t)q0;
       const uint32_t* w = reinterpret_cast<const uint32_t*>(stage) + (off >> 2);
-      const uint32_t d0 = w[0], d1 = w[1], d2 = w[2], d3 = w[3];
-      if (poff[k] & 2u) {
-        const uint32_t d4 = w[4];
-        win[k] = u32x4{__builtin_amdgcn_alignbyte(d1, d0, 2), __builtin_amdgcn_alignbyte(d2, d1, 2),
-                       __builtin_amdgcn_alignbyte(d3, d2, 2), __builtin_amdgcn_alignbyte(d4, d3, 2)};
-      } else {
-        win[k] = u32x4{d0, d1, d2, d3};
-      }
+      const uint32_t d0 = w[0], d1 = w[1], d2 = w[2], d3 = w[3], d4 = w[4];
+      const uint32_t sb = poff[k] & 3u;
+      win[k] = u32x4{__builtin_amdgcn_alignbyte(d1, d0, sb), __builtin_amdgcn_alignbyte(d2, d1, sb),
+                     __builtin_amdgcn_alignbyte(d3, d2, sb), __builtin_amdgcn_alignbyte(d4, d3, sb)};
     }
   }
   bool bad = false;
