@@ -163,46 +163,207 @@ __global__ __launch_bounds__(kThreads) void rle_clear_kernel(uint64_t* p, int64_
     p[i] = 0;
 }
 
+// Byte k of each of four words, gathered into one word: one column of a
+// 4x4 byte transpose (pixel-major RGBA words -> plane-major bytes).
+__device__ __forceinline__ uint32_t gather_byte(uint32_t a, uint32_t b, uint32_t c, uint32_t d,
+                                                int k) {
+  const int sh = 8 * k;
+  return ((a >> sh) & 0xFFu) | (((b >> sh) & 0xFFu) << 8) | (((c >> sh) & 0xFFu) << 16) |
+         (((d >> sh) & 0xFFu) << 24);
+}
+
+// Bit i (i < 4) set when byte i of x is nonzero.
+__device__ __forceinline__ uint32_t nonzero_bytes(uint32_t x) {
+  const uint32_t t = (((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+  return ((t >> 7) | (t >> 14) | (t >> 21) | (t >> 28)) & 0xFu;
+}
+
+// Bit j of the result is bit k of nibble j of the 64-bit value lo | hi << 32
+// (16 nibbles): one row of a 4 x 16 bit-matrix transpose.
+__device__ __forceinline__ uint32_t nibble_bits(uint32_t lo, uint32_t hi, int k) {
+  uint32_t x = (lo >> k) & 0x11111111u, y = (hi >> k) & 0x11111111u;
+  x = (x | (x >> 3)) & 0x03030303u;  y = (y | (y >> 3)) & 0x03030303u;
+  x = (x | (x >> 6)) & 0x000F000Fu;  y = (y | (y >> 6)) & 0x000F000Fu;
+  x = (x | (x >> 12)) & 0xFFu;       y = (y | (y >> 12)) & 0xFFu;
+  return x | (y << 8);
+}
+
+// DPP row shift left by D lanes inside rows of 16 lanes (lane r reads lane
+// r + D); lanes whose source lies outside the row keep `fill`.
+template <int D>
+__device__ __forceinline__ int row_shl_fill(int v, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, v, 0x100 + D, 0xF, 0xF, false);
+}
+
+// Inclusive scan over the 64 lanes: DPP inside rows of 16, then the row
+// totals of the lower rows (read lane by lane).
+__device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);
+  const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+  const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+  const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
+  const int row = (threadIdx.x % kWave) >> 4;
+  return v + (row >= 1 ? r0 : 0u) + (row >= 2 ? r1 : 0u) + (row >= 3 ? r2 : 0u);
+}
+
+// Exclusive workgroup scan of kW 32-bit words of packed counters that cannot
+// overflow; also returns the totals. `sh` holds 4 * kW words; two barriers.
+template <int kW>
+__device__ __forceinline__ void block_scan32(const uint32_t (&v)[kW], uint32_t (&ex)[kW],
+                                             uint32_t (&tot)[kW], uint32_t* sh) {
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  uint32_t inc[kW];
+#pragma unroll
+  for (int i = 0; i < kW; ++i) {
+    inc[i] = wave_incl_scan32(v[i]);
+    if (lane == kWave - 1) sh[4 * i + wave] = inc[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kW; ++i) {
+    uint32_t p = 0, t = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / kWave; ++w) {
+      const uint32_t x = sh[4 * i + w];
+      if (w < wave) p += x;
+      t += x;
+    }
+    ex[i] = p + inc[i] - v[i];
+    tot[i] = t;
+  }
+  __syncthreads();
+}
+
+// One compression slot: image s, block b, and the image's clamped ROI.
+struct CSlot {
+  int s, b, rx, ry, rw, rh;
+};
+
+__device__ __forceinline__ CSlot compress_slot(uint32_t g, int n, const int4* t_roi,
+                                               const uint32_t* t_slots, const uint32_t* t_incl,
+                                               int lane) {
+  CSlot c;
+  const uint64_t hit = __ballot(lane < n && g < t_incl[lane]);
+  c.s = uniform(__builtin_ctzll(hit));
+  c.b = uniform((int)(g - (t_incl[c.s] - t_slots[c.s])));
+  const int4 r = t_roi[c.s];
+  c.rx = uniform(r.x);
+  c.ry = uniform(r.y);
+  c.rw = uniform(r.z);
+  c.rh = uniform(r.w);
+  return c;
+}
+
+// Issues the loads of this lane's 16 pixels of slot c (zeros past the block).
+__device__ __forceinline__ void compress_load(const RleCArgs& a, const CSlot& c, int tid,
+                                              uint32_t (&col)[kPxPerLane],
+                                              uint32_t (&dep)[kPxPerLane]) {
+  const RleCImg& I = a.im[c.s];
+  const int64_t npx = (int64_t)c.rw * c.rh;
+  const int len = (int)imin64(kBlock, npx - (int64_t)c.b * kBlock);   // <= 0: no pixels
+  const int q0 = tid * kPxPerLane;
+  // the block's first pixel (uniform), then this lane's row by a 32-bit division
+  const int64_t qb = (int64_t)c.b * kBlock;
+  const int rw = c.rw > 0 ? c.rw : 1;
+  const int yb = uniform((int)(qb / rw));
+  const int xb = uniform((int)(qb - (int64_t)yb * rw));
+  const uint32_t xl = (uint32_t)xb + (uint32_t)q0;
+  const uint32_t dy = xl / (uint32_t)rw;
+  int yy = yb + (int)dy, xx = (int)(xl - dy * (uint32_t)rw);
+  const bool fast = (q0 + kPxPerLane <= len) && (xx + kPxPerLane <= rw);
+  if (fast) {
+    const int64_t off = (int64_t)(c.ry + yy) * I.pitch + c.rx + xx;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const u32x4 c4 = ld_u32x4(I.color + off + 4 * v);
+      col[4 * v + 0] = c4.x; col[4 * v + 1] = c4.y; col[4 * v + 2] = c4.z; col[4 * v + 3] = c4.w;
+      if (I.depth) {
+        const u32x4 d4 = ld_u32x4(I.depth + off + 4 * v);
+        dep[4 * v + 0] = d4.x; dep[4 * v + 1] = d4.y; dep[4 * v + 2] = d4.z; dep[4 * v + 3] = d4.w;
+      } else {
+        dep[4 * v + 0] = dep[4 * v + 1] = dep[4 * v + 2] = dep[4 * v + 3] = 0;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kPxPerLane; ++j) {
+      col[j] = 0;
+      dep[j] = 0;
+      if (q0 + j < len) {
+        const int64_t off = (int64_t)(c.ry + yy) * I.pitch + c.rx + xx;
+        col[j] = I.color[off];
+        if (I.depth) dep[j] = I.depth[off];
+        if (++xx == rw) { xx = 0; ++yy; }
+      }
+    }
+  }
+}
+
+// The tokens (run length - 1, value) of this lane's runs of one plane, from
+// token index idx on; 16-bit stores when the plane starts at an even offset.
+template <bool kEven>
+__device__ __forceinline__ void emit_tokens(uint8_t* stage, uint32_t off, uint32_t idx, uint32_t m,
+                                            const uint32_t (&pw)[4], int q0, int next_after) {
+  while (m) {
+    const int j = __builtin_ctz(m);
+    m &= m - 1u;
+    const int end = m ? q0 + __builtin_ctz(m) : next_after;
+    const uint32_t w = j < 4 ? pw[0] : j < 8 ? pw[1] : j < 12 ? pw[2] : pw[3];
+    const uint32_t tokv = (uint32_t)(end - q0 - j - 1) | (((w >> (8 * (j & 3))) & 0xFFu) << 8);
+    if (kEven) {
+      *reinterpret_cast<uint16_t*>(stage + off + 2 * idx) = (uint16_t)tokv;
+    } else {
+      stage[off + 2 * idx] = (uint8_t)tokv;
+      stage[off + 2 * idx + 1] = (uint8_t)(tokv >> 8);
+    }
+    ++idx;
+  }
+}
+
 __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t stage[kStage];
-  __shared__ uint64_t sh[8];
+  __shared__ uint32_t sh[16];
   __shared__ uint32_t s_excl;
-  const int tid = threadIdx.x;
-  const int lane = tid % kWave;
 
   // Slots: one per block of every image's ROI (an empty ROI still takes one
   // slot, whose workgroup writes the header-only stream). Wave 0 computes the
   // table (lane i: image i, n <= 64; one load, then a wave scan) into LDS.
   __shared__ int4 t_roi[kRleMax];
   __shared__ uint32_t t_slots[kRleMax], t_incl[kRleMax], t_total;
-  if (tid < kWave) {
-    int lx = 0, ly = 0, lw = 0, lh = 0;
-    uint32_t lslots = 0;
-    if (lane < a.n) {
-      const int W = a.im[lane].W, H = a.im[lane].H;
-      if (a.roi_dev) {
-        const int4 r = reinterpret_cast<const int4*>(a.roi_dev)[lane];
-        lx = min(max(r.x, 0), W);
-        ly = min(max(r.y, 0), H);
-        lw = min(max(r.z, 0), W - lx);
-        lh = min(max(r.w, 0), H - ly);
-        if (lw == 0 || lh == 0) { lx = 0; ly = 0; lw = 0; lh = 0; }
-      } else {
-        lw = W; lh = H;
+  {
+    const int tid = threadIdx.x, lane = tid % kWave;
+    if (tid < kWave) {
+      int lx = 0, ly = 0, lw = 0, lh = 0;
+      uint32_t lslots = 0;
+      if (lane < a.n) {
+        const int W = a.im[lane].W, H = a.im[lane].H;
+        if (a.roi_dev) {
+          const int4 r = reinterpret_cast<const int4*>(a.roi_dev)[lane];
+          lx = min(max(r.x, 0), W);
+          ly = min(max(r.y, 0), H);
+          lw = min(max(r.z, 0), W - lx);
+          lh = min(max(r.w, 0), H - ly);
+          if (lw == 0 || lh == 0) { lx = 0; ly = 0; lw = 0; lh = 0; }
+        } else {
+          lw = W; lh = H;
+        }
+        const uint32_t nb = (uint32_t)rle_nblocks((int64_t)lw * lh);
+        lslots = nb ? nb : 1;
       }
-      const uint32_t nb = (uint32_t)rle_nblocks((int64_t)lw * lh);
-      lslots = nb ? nb : 1;
-    }
-    uint32_t lincl = lslots;
+      uint32_t lincl = lslots;
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const uint32_t o = __shfl_up(lincl, d);
-      if (lane >= d) lincl += o;
+      for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = __shfl_up(lincl, d);
+        if (lane >= d) lincl += o;
+      }
+      t_roi[lane] = int4{lx, ly, lw, lh};
+      t_slots[lane] = lslots;
+      t_incl[lane] = lincl;
+      if (lane == kWave - 1) t_total = lincl;
     }
-    t_roi[lane] = int4{lx, ly, lw, lh};
-    t_slots[lane] = lslots;
-    t_incl[lane] = lincl;
-    if (lane == kWave - 1) t_total = lincl;
   }
   __syncthreads();
   const uint32_t total = t_total;
@@ -211,20 +372,23 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
   // A block waits only for smaller slots of its image; the smallest
   // unfinished slot always belongs to a running workgroup that has finished
   // its earlier slots, so the waits always end (and are bounded anyway).
+  // The pixels of a workgroup's next slot are loaded while it finishes the
+  // current one (look-back and writes).
+  uint32_t col[kPxPerLane], dep[kPxPerLane];
+  CSlot nx{0, 0, 0, 0, 0, 0};
+  if (blockIdx.x < total) {
+    nx = compress_slot(blockIdx.x, a.n, t_roi, t_slots, t_incl, threadIdx.x % kWave);
+    compress_load(a, nx, threadIdx.x, col, dep);
+  }
   for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
   // an opaque copy of the thread index: keeps per-lane values from being
   // hoisted out of the loop and held in registers across iterations
   int tid = threadIdx.x;
   __asm__ volatile("" : "+v"(tid));
   const int lane = tid % kWave;
-  int s, b, rx, ry, rw, rh;
-  {
-    const uint64_t hit = __ballot(lane < a.n && g < t_incl[lane]);
-    s = uniform(__builtin_ctzll(hit));
-    b = uniform((int)(g - (t_incl[s] - t_slots[s])));
-    const int4 r = t_roi[s];
-    rx = uniform(r.x); ry = uniform(r.y); rw = uniform(r.z); rh = uniform(r.w);
-  }
+  const CSlot c = nx;
+  const int s = c.s, b = c.b, rx = c.rx, ry = c.ry, rw = c.rw, rh = c.rh;
+  const bool more = g + gridDim.x < total;
   {
     const RleCImg I = a.im[s];
     const int np = I.depth ? 8 : 4;
@@ -233,6 +397,10 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
     const uint64_t P0 = rle_p0(nb, np);
     uint8_t* out = I.out;
     if (nb == 0) {
+      if (more) {
+        nx = compress_slot(g + gridDim.x, a.n, t_roi, t_slots, t_incl, lane);
+        compress_load(a, nx, tid, col, dep);
+      }
       if (tid < 8) {
         const uint32_t hdr[8] = {kRleMagic, (uint32_t)rx, (uint32_t)ry, 0u, 0u,
                                  (uint32_t)np | (a.swizzle ? 0x100u : 0u), (uint32_t)kBlock, 0u};
@@ -241,75 +409,49 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
       if (tid == 0) a.out_size[s] = 32;
     } else {
       const int len = (int)imin64(kBlock, npx - (int64_t)b * kBlock);
-      // ---- load this lane's 16 pixels
-      uint32_t col[kPxPerLane], dep[kPxPerLane];
       const int q0 = tid * kPxPerLane;   // block-relative first pixel
-      {
-        const int64_t q = (int64_t)b * kBlock + q0;
-        int yy = (int)(q / rw), xx = (int)(q - (int64_t)yy * rw);
-        const bool fast = (q0 + kPxPerLane <= len) && (xx + kPxPerLane <= rw);
-        if (fast) {
-          const int64_t off = (int64_t)(ry + yy) * I.pitch + rx + xx;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const u32x4 c4 = ld_u32x4(I.color + off + 4 * v);
-            col[4 * v + 0] = c4.x; col[4 * v + 1] = c4.y; col[4 * v + 2] = c4.z; col[4 * v + 3] = c4.w;
-            if (np == 8) {
-              const u32x4 d4 = ld_u32x4(I.depth + off + 4 * v);
-              dep[4 * v + 0] = d4.x; dep[4 * v + 1] = d4.y; dep[4 * v + 2] = d4.z; dep[4 * v + 3] = d4.w;
-            } else {
-              dep[4 * v + 0] = dep[4 * v + 1] = dep[4 * v + 2] = dep[4 * v + 3] = 0;
-            }
-          }
-        } else {
-#pragma unroll
-          for (int j = 0; j < kPxPerLane; ++j) {
-            col[j] = 0;
-            dep[j] = 0;
-            if (q0 + j < len) {
-              const int64_t off = (int64_t)(ry + yy) * I.pitch + rx + xx;
-              col[j] = I.color[off];
-              if (np == 8) dep[j] = I.depth[off];
-              if (++xx == rw) { xx = 0; ++yy; }
-            }
-          }
-        }
-      }
       if (a.swizzle) {
 #pragma unroll
         for (int j = 0; j < kPxPerLane; ++j) col[j] = swizzle_bits(col[j]);
       }
       const uint32_t pcol = __shfl_up(col[kPxPerLane - 1], 1);
       const uint32_t pdep = __shfl_up(dep[kPxPerLane - 1], 1);
+      // plane words, made when needed: byte j of pw[j / 4] is plane k of pixel j
+      auto plane_words = [&](int k, uint32_t (&pw)[4]) {
+        const uint32_t* w = k < 4 ? col : dep;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          pw[i] = gather_byte(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3], k & 3);
+      };
       const bool seg_start = (tid % (kSeg / kPxPerLane)) == 0;
       const int nvalid = min(kPxPerLane, max(0, len - q0));
       const uint32_t vmask = (1u << nvalid) - 1u;
 
-      // ---- run starts and counts per plane
+      // ---- run starts (byte != previous byte, or a segment start) and counts:
+      // per pixel, which bytes differ from the previous pixel's (a nibble),
+      // then the 16 nibbles transposed into one 16-bit mask per plane
+      uint32_t nc_lo = 0, nc_hi = 0, nd_lo = 0, nd_hi = 0;
+#pragma unroll
+      for (int j = 0; j < kPxPerLane; ++j) {
+        const uint32_t c = nonzero_bytes(col[j] ^ (j ? col[j - 1] : pcol));
+        const uint32_t d = nonzero_bytes(dep[j] ^ (j ? dep[j - 1] : pdep));
+        if (j < 8) { nc_lo |= c << (4 * j); nd_lo |= d << (4 * j); }
+        else { nc_hi |= c << (4 * (j - 8)); nd_hi |= d << (4 * (j - 8)); }
+      }
       uint32_t masks[8];
-      uint64_t cnt_lo = 0, cnt_hi = 0;
+      uint32_t cnt[4] = {0, 0, 0, 0};
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         masks[k] = 0;
         if (k >= np) continue;
-        const uint32_t* w = k < 4 ? col : dep;
-        uint32_t m = 0;
-        uint32_t prev = byte_of(k < 4 ? pcol : pdep, k);
-#pragma unroll
-        for (int j = 0; j < kPxPerLane; ++j) {
-          const uint32_t c = byte_of(w[j], k);
-          const bool st = (j == 0) ? (seg_start || c != prev) : (c != prev);
-          m |= (uint32_t)st << j;
-          prev = c;
-        }
+        uint32_t m = k < 4 ? nibble_bits(nc_lo, nc_hi, k) : nibble_bits(nd_lo, nd_hi, k - 4);
+        if (seg_start) m |= 1u;
         m &= vmask;
         masks[k] = m;
-        const uint64_t c = (uint64_t)__builtin_popcount(m);
-        if (k < 4) cnt_lo |= c << (16 * k);
-        else cnt_hi |= c << (16 * (k - 4));
+        cnt[k >> 1] |= (uint32_t)__builtin_popcount(m) << (16 * (k & 1));
       }
-      uint64_t ex_lo, ex_hi, tot_lo, tot_hi;
-      block_scan2(cnt_lo, cnt_hi, ex_lo, ex_hi, tot_lo, tot_hi, sh);
+      uint32_t ex[4], tot[4];
+      block_scan32<4>(cnt, ex, tot, sh);
 
       // ---- plane sizes and offsets (uniform)
       uint32_t size[8], poff[8];
@@ -319,7 +461,7 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
         size[k] = 0;
         poff[k] = total;
         if (k >= np) continue;
-        const uint32_t ntok = field16(tot_lo, tot_hi, k);
+        const uint32_t ntok = (tot[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
         size[k] = (2 * ntok < (uint32_t)len) ? 2 * ntok : (uint32_t)len;
         total += size[k];
       }
@@ -327,52 +469,37 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
 
       // ---- stage the encoded block in LDS
       const int seg_end = min(len, ((q0 / kSeg) + 1) * kSeg);
-      const int lig = tid % (kSeg / kPxPerLane);   // lane within its 256-pixel segment
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         if (k >= np) continue;
-        const uint32_t* w = k < 4 ? col : dep;
         const uint32_t m = masks[k];
         const uint32_t off = poff[k];
+        uint32_t pw[4];
+        plane_words(k, pw);
         if (size[k] != (uint32_t)len) {
-          // first start of this lane, then the suffix minimum over later lanes
+          // a run ends at the next start: in this lane, else the first start
+          // of the following lanes of the segment (a suffix minimum over the
+          // lane's DPP row), else the segment end
           int fs = m ? q0 + __builtin_ctz(m) : seg_end;
-#pragma unroll
-          for (int d = 1; d < kSeg / kPxPerLane; d <<= 1) {
-            const int o = __shfl_down(fs, d, kSeg / kPxPerLane);
-            if (lig + d < kSeg / kPxPerLane) fs = min(fs, o);
-          }
-          const int nxt = __shfl_down(fs, 1, kSeg / kPxPerLane);
-          const int next_after = (lig == kSeg / kPxPerLane - 1) ? seg_end : nxt;
-          const uint32_t tok0 = field16(ex_lo, ex_hi, k);
-#pragma unroll
-          for (int j = 0; j < kPxPerLane; ++j) {
-            if ((m >> j) & 1u) {
-              const uint32_t rest = m >> (j + 1);
-              const int end = rest ? q0 + j + 1 + __builtin_ctz(rest) : next_after;
-              const uint32_t idx = tok0 + __builtin_popcount(m & ((1u << j) - 1u));
-              const uint32_t tokv = (uint32_t)(end - (q0 + j) - 1) | (byte_of(w[j], k) << 8);
-              if ((off & 1u) == 0) {   // uniform: one 16-bit store per token
-                *reinterpret_cast<uint16_t*>(stage + off + 2 * idx) = (uint16_t)tokv;
-              } else {
-                stage[off + 2 * idx] = (uint8_t)tokv;
-                stage[off + 2 * idx + 1] = (uint8_t)(tokv >> 8);
-              }
-            }
-          }
+          fs = min(fs, row_shl_fill<1>(fs, seg_end));
+          fs = min(fs, row_shl_fill<2>(fs, seg_end));
+          fs = min(fs, row_shl_fill<4>(fs, seg_end));
+          fs = min(fs, row_shl_fill<8>(fs, seg_end));
+          const int next_after = row_shl_fill<1>(fs, seg_end);
+          const uint32_t tok0 = (ex[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+          if ((off & 1u) == 0)
+            emit_tokens<true>(stage, off, tok0, m, pw, q0, next_after);
+          else
+            emit_tokens<false>(stage, off, tok0, m, pw, q0, next_after);
         } else if ((off & 3u) == 0 && q0 + kPxPerLane <= len) {
           // raw plane, 4-byte aligned: four 32-bit stores per lane
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const uint32_t word = byte_of(w[4 * v], k) | (byte_of(w[4 * v + 1], k) << 8) |
-                                  (byte_of(w[4 * v + 2], k) << 16) |
-                                  (byte_of(w[4 * v + 3], k) << 24);
-            *reinterpret_cast<uint32_t*>(stage + off + q0 + 4 * v) = word;
-          }
+          for (int i = 0; i < 4; ++i)
+            *reinterpret_cast<uint32_t*>(stage + off + q0 + 4 * i) = pw[i];
         } else {
 #pragma unroll
           for (int j = 0; j < kPxPerLane; ++j)
-            if (q0 + j < len) stage[off + q0 + j] = (uint8_t)byte_of(w[j], k);
+            if (q0 + j < len) stage[off + q0 + j] = (uint8_t)(pw[j >> 2] >> (8 * (j & 3)));
         }
       }
       if (tid < (int)(padded - total)) stage[total + tid] = 0;
@@ -423,6 +550,12 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
                                __HIP_MEMORY_SCOPE_AGENT);
         }
         if (lane == 0) s_excl = excl;
+      }
+      // the next slot's pixels go in flight: waves 1..3 during the look-back,
+      // wave 0 after it (its flag loads must not wait behind these loads)
+      if (more) {
+        nx = compress_slot(g + gridDim.x, a.n, t_roi, t_slots, t_incl, lane);
+        compress_load(a, nx, tid, col, dep);
       }
       __syncthreads();
       const uint32_t excl = s_excl;
