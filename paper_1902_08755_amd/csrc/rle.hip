@@ -155,6 +155,7 @@ static_assert(sizeof(RleCArgs) <= 4096, "kernel arguments must fit in 4 KiB");
 // look-back flag: status (2 bits) << 32 | value (32 bits); 0 = not ready.
 // The flags are cleared by rle_clear_kernel before every compression.
 constexpr uint64_t kAgg = 1, kIncl = 2;
+constexpr int kLookback = 4;   // flags per lane per look-back step
 __device__ __forceinline__ uint64_t mkflag(uint64_t st, uint32_t v) { return (st << 32) | v; }
 
 __global__ __launch_bounds__(kThreads) void rle_clear_kernel(uint64_t* p, int64_t n) {
@@ -466,6 +467,12 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
         total += size[k];
       }
       const uint32_t padded = (uint32_t)align16(total);
+      // the block's size is known: publish it now (block 0: as the inclusive
+      // prefix), so that successors need not wait for the staging below
+      uint64_t* flags = a.flags + I.flag_base;
+      if (tid == 0)
+        __hip_atomic_store(&flags[b], mkflag(b == 0 ? kIncl : kAgg, padded), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 
       // ---- stage the encoded block in LDS
       const int seg_end = min(len, ((q0 / kSeg) + 1) * kSeg);
@@ -505,32 +512,38 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
       if (tid < (int)(padded - total)) stage[total + tid] = 0;
 
       // ---- decoupled look-back for the payload offset: wave 0 reads the
-      // flags of 64 predecessors at once, sums the aggregates up to the
-      // nearest inclusive prefix, and moves the window back if it has none
+      // flags of 256 predecessors at once (4 per lane, each load instruction
+      // contiguous over the lanes), sums the aggregates up to the nearest
+      // inclusive prefix, and moves the window back if it has none
       if (tid < kWave) {
-        uint64_t* flags = a.flags + I.flag_base;
         uint32_t excl = 0;
-        if (b == 0) {
-          if (lane == 0)
-            __hip_atomic_store(&flags[0], mkflag(kIncl, padded), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-          if (lane == 0)
-            __hip_atomic_store(&flags[b], mkflag(kAgg, padded), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-          int top = b - 1;   // lane l reads predecessor top - l
+        if (b != 0) {
+          int top = b - 1;   // flag i of lane l: predecessor top - (64 i + l)
           uint32_t spins = 0;
           while (true) {
-            const int p = top - lane;
-            uint64_t f = mkflag(kIncl, 0);   // before block 0: an empty prefix
-            if (p >= 0) f = __hip_atomic_load(&flags[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t st = (f >> 32) & 3u;
-            const bool ready = st != 0;
-            const uint64_t incl = __ballot(ready && st == kIncl);
-            const uint64_t notready = __ballot(!ready);
-            const int first = incl ? __builtin_ctzll(incl) : kWave;
-            const uint64_t need = first >= kWave - 1 ? ~0ull : ((2ull << first) - 1ull);
-            if (notready & need) {
+            uint64_t f[kLookback];
+#pragma unroll
+            for (int i = 0; i < kLookback; ++i) {
+              const int p = top - (kWave * i + lane);
+              f[i] = mkflag(kIncl, 0);   // before block 0: an empty prefix
+              if (p >= 0) f[i] = __hip_atomic_load(&flags[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            // the nearest inclusive prefix (distance 64 i + lane), and whether
+            // every flag up to it is ready
+            int first = kWave * kLookback;
+            bool waiting = false;
+#pragma unroll
+            for (int i = kLookback - 1; i >= 0; --i) {
+              const uint64_t st = (f[i] >> 32) & 3u;
+              const uint64_t incl = __ballot(st == kIncl);
+              if (incl) first = kWave * i + (int)__builtin_ctzll(incl);
+            }
+#pragma unroll
+            for (int i = 0; i < kLookback; ++i) {
+              const uint64_t st = (f[i] >> 32) & 3u;
+              if (__ballot(st == 0 && kWave * i + lane <= first)) waiting = true;
+            }
+            if (waiting) {
               if (++spins > (1u << 20)) {
                 if (lane == 0 && a.status) a.status[s] = CMP_ETIMEOUT;
                 break;
@@ -538,12 +551,15 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
               __builtin_amdgcn_s_sleep(1);
               continue;
             }
-            uint32_t v = lane <= first ? (uint32_t)f : 0u;
+            uint32_t v = 0;
+#pragma unroll
+            for (int i = 0; i < kLookback; ++i)
+              if (kWave * i + lane <= first) v += (uint32_t)f[i];
 #pragma unroll
             for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
             excl += v;
-            if (first < kWave) break;
-            top -= kWave;
+            if (first < kWave * kLookback) break;
+            top -= kWave * kLookback;
           }
           if (lane == 0)
             __hip_atomic_store(&flags[b], mkflag(kIncl, excl + padded), __ATOMIC_RELAXED,
