@@ -377,9 +377,11 @@ def main():
         wl = synth.depth_ramps_full(seed=2, n=16, W=1920, H=1080, device=dev)
         frames.append(Frame(wl, dev))
     s_obj = torch.cuda.current_stream()
-    # one checked pass: ROIs and stream sizes for the byte counts
-    for k in range(4):
-        frames[0].stage(k, s_obj.cuda_stream)
+    # one pass over every copy (each holds valid ROIs and streams from here
+    # on), checked on the first: ROIs and stream sizes for the byte counts
+    for f in frames:
+        for k in range(4):
+            f.stage(k, s_obj.cuda_stream)
     torch.cuda.synchronize()
     rois = [tuple(r) for r in frames[0].roi.cpu().tolist()]
     assert rois == [im.true_roi for im in frames[0].images], "ROI detection mismatch"

@@ -57,13 +57,32 @@ __host__ __device__ inline uint64_t rle_p0(uint64_t nb, int np) {
 
 // ------------------------------------------------------------- helpers
 __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
-  const int lane = threadIdx.x % kWave;
+  // DPP inside rows of 16 lanes (both halves of the word, then a 64-bit
+  // add), then the row totals of the lower rows read lane by lane
 #pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const uint64_t o = __shfl_up(v, d);
-    if (lane >= d) v += o;
+  for (int d = 1; d < 16; d <<= 1) {
+    uint32_t lo = 0, hi = 0;
+    switch (d) {
+      case 1: lo = __builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);
+              hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x111, 0xF, 0xF, true); break;
+      case 2: lo = __builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);
+              hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x112, 0xF, 0xF, true); break;
+      case 4: lo = __builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);
+              hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x114, 0xF, 0xF, true); break;
+      default: lo = __builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);
+               hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x118, 0xF, 0xF, true); break;
+    }
+    v += ((uint64_t)hi << 32) | lo;
   }
-  return v;
+  const uint32_t vlo = (uint32_t)v, vhi = (uint32_t)(v >> 32);
+  const uint64_t r0 = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)vhi, 15) << 32) |
+                      (uint32_t)__builtin_amdgcn_readlane((int)vlo, 15);
+  const uint64_t r1 = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)vhi, 31) << 32) |
+                      (uint32_t)__builtin_amdgcn_readlane((int)vlo, 31);
+  const uint64_t r2 = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)vhi, 47) << 32) |
+                      (uint32_t)__builtin_amdgcn_readlane((int)vlo, 47);
+  const int row = (threadIdx.x % kWave) >> 4;
+  return v + (row >= 1 ? r0 : 0ull) + (row >= 2 ? r1 : 0ull) + (row >= 3 ? r2 : 0ull);
 }
 
 // Exclusive workgroup scan of two packed words (4 x 16-bit counters each);
@@ -666,13 +685,26 @@ __device__ __forceinline__ uint32_t row_shr(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x110 + D, 0xF, 0xF, true);
 }
 
-__global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs a) {
+__global__ __launch_bounds__(kThreads, 4) void rle_decompress_kernel(const RleDArgs a) {
   // the block payload, later the bytes of its runs at their start positions
   __shared__ __attribute__((aligned(16))) uint8_t stage[kStage];
   __shared__ __attribute__((aligned(16))) uint32_t starts[8][kBlock / 32];   // run-start bits
   __shared__ uint64_t sh[12];
   __shared__ int32_t s_bad[kThreads / kWave];
+  // byte selectors that fill a word from its run starts: for start nibble n,
+  // byte j takes the word's byte at the last start <= j, else byte 3 of the
+  // previous word (v_perm numbering: 0..3 this word, 4..7 the previous one)
+  __shared__ uint32_t fill_sel[16];
   const int tid = threadIdx.x;
+  if (tid < 16) {
+    uint32_t sel = 0;
+    int last = 7;
+    for (int j = 0; j < 4; ++j) {
+      if ((tid >> j) & 1) last = j;
+      sel |= (uint32_t)last << (8 * j);
+    }
+    fill_sel[tid] = sel;
+  }
   const int lane = tid % kWave;
 
   // Wave 0 reads and checks the header of stream i in lane i (n <= 64) into
@@ -825,12 +857,14 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       if (tokmask & (1u << k)) {
-        const int ntok = (int)(size[k] / 2);
+        const int nv = min(8, max(0, (int)(size[k] / 2) - tid * 8));   // this lane's tokens
         const uint32_t wv[4] = {win[k].x, win[k].y, win[k].z, win[k].w};
-        uint32_t sum = 0;
+        uint32_t sum = (uint32_t)nv;   // + the (length - 1) bytes of its tokens
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-          if (tid * 8 + j < ntok) sum += ((wv[j >> 1] >> (16 * (j & 1))) & 0xFFu) + 1u;
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t keep = (nv > 2 * i ? 0xFFu : 0u) | (nv > 2 * i + 1 ? 0xFF0000u : 0u);
+          sum = __builtin_amdgcn_sad_u8(wv[i] & keep, 0u, sum);
+        }
         v3[fld_word(k)] |= (uint64_t)sum << fld_shift(k);
       }
     }
@@ -848,19 +882,20 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       if (tokmask & (1u << k)) {
-        const int ntok = (int)(size[k] / 2);
+        const int nv = min(8, max(0, (int)(size[k] / 2) - tid * 8));
         const uint32_t wv[4] = {win[k].x, win[k].y, win[k].z, win[k].w};
         uint32_t pos = (uint32_t)((ex3[fld_word(k)] >> fld_shift(k)) & kFld);
+        uint8_t* vals = stage + k * kBlock;
+        uint32_t* bits = starts[k];
+        auto put = [&](uint32_t t) {
+          vals[pos] = (uint8_t)(t >> 8);
+          __hip_atomic_fetch_or(&bits[pos >> 5], 1u << (pos & 31), __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_WORKGROUP);
+          pos += (t & 0xFFu) + 1u;
+        };
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          if (tid * 8 + j < ntok) {
-            const uint32_t t = wv[j >> 1] >> (16 * (j & 1));
-            stage[k * kBlock + pos] = (uint8_t)(t >> 8);
-            __hip_atomic_fetch_or(&starts[k][pos >> 5], 1u << (pos & 31), __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_WORKGROUP);
-            pos += (t & 0xFFu) + 1u;
-          }
-        }
+        for (int j = 0; j < 8; ++j)
+          if (j < nv) put(wv[j >> 1] >> (16 * (j & 1)));
       }
     }
     __syncthreads();
@@ -883,13 +918,15 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
         y = row_shr<2>(x); if (!(x & 0x100u)) x = y;
         y = row_shr<4>(x); if (!(x & 0x100u)) x = y;
         y = row_shr<8>(x); if (!(x & 0x100u)) x = y;
-        uint32_t cur = row_shr<1>(x) & 0xFFu;
         if ((tid & 15) == 0 && q0 < len && !(m & 1u)) bad = true;   // a run crosses a segment
-        uint32_t o[4] = {0, 0, 0, 0};
+        // word by word: each byte from the last start in the word, else the
+        // previous word's last byte (the value entering the lane for word 0)
+        uint32_t o[4];
+        uint32_t prev = row_shr<1>(x) << 24;
 #pragma unroll
-        for (int j = 0; j < kPxPerLane; ++j) {
-          if (m & (1u << j)) cur = (dv[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-          o[j >> 2] |= cur << (8 * (j & 3));
+        for (int i = 0; i < 4; ++i) {
+          prev = __builtin_amdgcn_perm(prev, dv[i], fill_sel[(m >> (4 * i)) & 0xFu]);
+          o[i] = prev;
         }
         win[k] = u32x4{o[0], o[1], o[2], o[3]};
       }
@@ -924,8 +961,12 @@ __global__ __launch_bounds__(kThreads) void rle_decompress_kernel(const RleDArgs
   }
   // ---- write the pixels (row-major over the ROI)
   if (q0 < len) {
-    const int64_t q = (int64_t)b * kBlock + q0;
-    int yy = (int)(q / rw), xx = (int)(q - (int64_t)yy * rw);
+    // the block's first pixel (uniform), then this lane's by a 32-bit division
+    const int64_t qb = (int64_t)b * kBlock;
+    const int yb = uniform((int)(qb / rw)), xb = uniform((int)(qb - (int64_t)yb * rw));
+    const uint32_t xl = (uint32_t)xb + (uint32_t)q0;
+    const uint32_t dy = xl / (uint32_t)rw;
+    int yy = yb + (int)dy, xx = (int)(xl - dy * (uint32_t)rw);
     const bool fast = (q0 + kPxPerLane <= len) && (xx + kPxPerLane <= rw);
     if (fast) {
       const int64_t o = (int64_t)yy * I.pitch + xx;
