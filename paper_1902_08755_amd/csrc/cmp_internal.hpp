@@ -89,6 +89,25 @@ __device__ __forceinline__ int wave_max(int v) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// The segment holding workgroup blk: the last i < n whose first workgroup
+// begin_of(i) is <= blk (begin_of(0) == 0, ascending). Every begin_of(i) is
+// read up front (independent scalar loads from the kernel arguments) rather
+// than one after another, which costs a cache miss per step on a CU's first
+// workgroup.
+template <int kN, typename F>
+__device__ __forceinline__ int count_begins_le(F begin_of, int n, int blk) {
+  int r = 0;
+#pragma unroll
+  for (int i = 1; i < kN; ++i) r += (i < n && begin_of(i) <= blk) ? 1 : 0;
+  return r;
+}
+template <typename F>
+__device__ __forceinline__ int segment_of(F begin_of, int n, int blk) {
+  if (n <= 1) return 0;
+  if (n <= 16) return count_begins_le<16>(begin_of, n, blk);
+  return count_begins_le<64>(begin_of, n, blk);
+}
+
 // The placement of contributor i: the host rectangle, or the device one
 // (clamped to the host rectangle's size, which bounds the buffer).
 __device__ __forceinline__ void placement(const int32_t* roi_dev, int idx, int32_t hx, int32_t hy,

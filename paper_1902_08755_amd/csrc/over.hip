@@ -27,7 +27,7 @@ __device__ __forceinline__ void region_tile(const Region* reg, int nreg, int til
                                             int& x0, int& y0, int& tw, int& th) {
   const int blk = blockIdx.x;
   int r = 0;
-  while (r + 1 < nreg && reg[r + 1].tile_begin <= blk) ++r;
+  r = segment_of([&](int i) { return reg[i].tile_begin; }, nreg, blk);
   const Region R = reg[r];
   const int local = blk - R.tile_begin;
   const int tiles_x = (R.w + tile_w - 1) / tile_w;

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kThreads) void roi_kernel(const RoiArgs a) {
   constexpr int ppu = 16 / bpp;  // pixels per 16-byte unit
   const int blk = blockIdx.x;
   int s = 0;
-  while (s + 1 < a.n && a.im[s + 1].wg_begin <= blk) ++s;
+  s = segment_of([&](int i) { return a.im[i].wg_begin; }, a.n, blk);
   const RoiImg I = a.im[s];
   const int local = blk - I.wg_begin;
   const int y0 = local * I.rows;
@@ -104,49 +104,31 @@ __global__ __launch_bounds__(kThreads) void roi_kernel(const RoiArgs a) {
     const int dq = kThreads / full_units, dr = kThreads - dq * full_units;
     int ry = (int)threadIdx.x / full_units;
     int u = (int)threadIdx.x - ry * full_units;
-    // two batches in registers: the next one is in flight while this one is
-    // examined
-    u32x4 v[2][kRoiBatch];
-    int xs[2][kRoiBatch], ys[2][kRoiBatch];
-    auto issue = [&](int t0, u32x4 (&vv)[kRoiBatch], int (&xx)[kRoiBatch], int (&yy)[kRoiBatch]) {
+    for (int t0 = threadIdx.x; t0 < uwork; t0 += kThreads * kRoiBatch) {
+      u32x4 v[kRoiBatch];
+      int xs[kRoiBatch], ys[kRoiBatch];
 #pragma unroll
       for (int k = 0; k < kRoiBatch; ++k) {
         const bool ok = t0 + k * kThreads < uwork;
-        xx[k] = ok ? u * ppu : -1;
-        yy[k] = y0 + ry;
+        xs[k] = ok ? u * ppu : -1;
+        ys[k] = y0 + ry;
         const u32x4* row =
             reinterpret_cast<const u32x4*>(base + (int64_t)(y0 + (ok ? ry : 0)) * row_bytes);
-        vv[k] = row[ok ? u : 0];
+        v[k] = row[ok ? u : 0];
         u += dr;
         ry += dq;
         if (u >= full_units) { u -= full_units; ++ry; }
       }
-    };
-    auto examine = [&](const u32x4 (&vv)[kRoiBatch], const int (&xx)[kRoiBatch],
-                       const int (&yy)[kRoiBatch]) {
 #pragma unroll
       for (int k = 0; k < kRoiBatch; ++k) {
-        const uint32_t m = xx[k] >= 0 ? unit_mask<MODE>(vv[k]) : 0u;
+        const uint32_t m = xs[k] >= 0 ? unit_mask<MODE>(v[k]) : 0u;
         if (m) {
-          minx = min(minx, xx[k] + (int)__builtin_ctz(m));
-          maxx = max(maxx, xx[k] + 31 - (int)__builtin_clz(m));
-          miny = min(miny, yy[k]);
-          maxy = max(maxy, yy[k]);
+          minx = min(minx, xs[k] + (int)__builtin_ctz(m));
+          maxx = max(maxx, xs[k] + 31 - (int)__builtin_clz(m));
+          miny = min(miny, ys[k]);
+          maxy = max(maxy, ys[k]);
         }
       }
-    };
-    constexpr int kStep = kThreads * kRoiBatch;
-    int t0 = threadIdx.x;
-    issue(t0, v[0], xs[0], ys[0]);
-    while (true) {
-      if (t0 + kStep < uwork) issue(t0 + kStep, v[1], xs[1], ys[1]);
-      examine(v[0], xs[0], ys[0]);
-      t0 += kStep;
-      if (t0 >= uwork) break;
-      if (t0 + kStep < uwork) issue(t0 + kStep, v[0], xs[0], ys[0]);
-      examine(v[1], xs[1], ys[1]);
-      t0 += kStep;
-      if (t0 >= uwork) break;
     }
   }
   // The remaining pixels of each row (all of them when rows are not 16-byte
@@ -267,7 +249,7 @@ __global__ __launch_bounds__(kThreads) void roi_grid_kernel(const GridArgs a) {
   __shared__ uint8_t flags[kGridChunkCells];
   const int blk = blockIdx.x;
   int s = 0;
-  while (s + 1 < a.n && a.im[s + 1].wg_begin <= blk) ++s;
+  s = segment_of([&](int i) { return a.im[i].wg_begin; }, a.n, blk);
   const GridImg I = a.im[s];
   const int local = blk - I.wg_begin;
   const int band = local / I.chunks, chunk = local - band * I.chunks;

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kThreads) void average_kernel(const AvgArgs a) {
   // region and tile of this workgroup
   const int blk = blockIdx.x;
   int r = 0;
-  while (r + 1 < a.nreg && a.reg[r + 1].tile_begin <= blk) ++r;
+  r = segment_of([&](int i) { return a.reg[i].tile_begin; }, a.nreg, blk);
   const Region R = a.reg[r];
   const int local = blk - R.tile_begin;
   const int tiles_x = (R.w + a.tile_w - 1) / a.tile_w;
