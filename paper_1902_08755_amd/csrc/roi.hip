@@ -205,10 +205,10 @@ __global__ __launch_bounds__(kThreads) void roi_kernel(const RoiArgs a) {
   }
 }
 
-// Rows per workgroup: about 128 KiB of reads per workgroup.
+// Rows per workgroup: about 256 KiB of reads per workgroup.
 static int roi_rows(const cmp_image& I, int bpp) {
   const int64_t row_bytes = (int64_t)(I.roi.w > 0 ? I.roi.w : 1) * bpp;
-  int64_t r = (128 * 1024 + row_bytes - 1) / row_bytes;
+  int64_t r = (256 * 1024 + row_bytes - 1) / row_bytes;
   if (r < 1) r = 1;
   if (r > I.roi.h) r = I.roi.h > 0 ? I.roi.h : 1;
   return (int)r;
