@@ -58,6 +58,7 @@ struct BatchArgs {
 
 __global__ __launch_bounds__(kThreads) void batch_kernel(const BatchArgs a) {
   __shared__ int s_item;
+  __shared__ DepthRec s_rec[kPlaceMax];   // contributors of the current depth job
   const int tid = threadIdx.x;
   while (true) {
     if (tid == 0)
@@ -69,15 +70,30 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const BatchArgs a) {
     const Item I = a.items[it];
     const JobRec& J = a.jobs[uniform(I.job)];
     const int t1 = uniform(I.tile0) + uniform(I.ntiles);
+    if (J.kind == 0) {
+      // contributors in chunks of kPlaceMax staged in LDS; later chunks
+      // combine with the output of earlier ones (the planner requires a
+      // depth buffer when there is more than one chunk)
+      const int jn = uniform(J.n);
+      for (int c0 = 0; c0 < jn || c0 == 0; c0 += kPlaceMax) {
+        const int cn = min(kPlaceMax, jn - c0);
+        if (c0 > 0) __syncthreads();   // the previous chunk's records are no longer read
+        stage_contributors(DepthSrc{a.ddesc + J.desc_off + c0, nullptr, 0}, cn, s_rec);
+        for (int tile = uniform(I.tile0); tile < t1; ++tile) {
+          const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
+          const int x0 = J.vx + tx * J.tile_w, y0 = J.vy + ty * J.tile_h;
+          const int tw = min(J.tile_w, J.vx + J.vw - x0), th = min(J.tile_h, J.vy + J.vh - y0);
+          depth_tile(s_rec, cn, x0, y0, tw, th, (uint32_t*)J.out_color, J.out_depth, J.out_pitch,
+                     J.vx, J.vy, c0 > 0);
+        }
+      }
+      continue;
+    }
     for (int tile = uniform(I.tile0); tile < t1; ++tile) {
       const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
       const int x0 = J.vx + tx * J.tile_w, y0 = J.vy + ty * J.tile_h;
       const int tw = min(J.tile_w, J.vx + J.vw - x0), th = min(J.tile_h, J.vy + J.vh - y0);
-      if (J.kind == 0) {
-        const DepthSrc src{a.ddesc + J.desc_off, nullptr, 0};
-        depth_tile(src, J.n, x0, y0, tw, th, (uint32_t*)J.out_color, J.out_depth, J.out_pitch,
-                   J.vx, J.vy, false);
-      } else if (J.fmt == CMP_RGBA32F) {
+      if (J.fmt == CMP_RGBA32F) {
         over_tile_seq<CMP_RGBA32F>(a.odesc + J.desc_off, J.n, x0, y0, tw, th, (float*)J.out_color,
                                    J.out_pitch, J.vx, J.vy, false);
       } else {
@@ -190,6 +206,10 @@ static cmp_status validate_job(const cmp_job& j, int idx) {
   CMP_REQUIRE(j.out_pitch >= j.viewport.w, "job %d: out_pitch < viewport.w", idx);
   cmp_status st = j.kind == 0 ? validate_depth_inputs(j.in, j.n)
                               : validate_over_inputs(j.in, j.n, j.fmt, j.order_b2f);
+  if (st == CMP_OK && j.kind == 0)
+    CMP_REQUIRE(j.n <= kPlaceMax || j.out_depth,
+                "job %d: out_depth is required when n > %d (it carries the result between "
+                "contributor chunks)", idx, kPlaceMax);
   if (st != CMP_OK) return st;
   if (j.kind == 0)
     CMP_REQUIRE(((uintptr_t)j.out_color & 3) == 0 && ((uintptr_t)j.out_depth & 3) == 0,

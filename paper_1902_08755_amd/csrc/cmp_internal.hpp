@@ -88,6 +88,15 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  return reinterpret_cast<T*>(uniform64((int64_t)reinterpret_cast<uintptr_t>(p)));
+}
 
 // The segment holding workgroup blk: the last i < n whose first workgroup
 // begin_of(i) is <= blk (begin_of(0) == 0, ascending). Every begin_of(i) is

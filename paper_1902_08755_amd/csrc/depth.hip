@@ -8,6 +8,7 @@
 namespace cmp {
 
 constexpr int kDepthPerPass = 48;
+static_assert(kDepthPerPass <= kPlaceMax, "placements of a pass are staged in LDS");
 
 struct DepthArgs {
   DepthDesc c[kDepthPerPass];
@@ -43,7 +44,9 @@ __global__ __launch_bounds__(kThreads) void depth_kernel(const DepthArgs a) {
   int x0, y0, tw, th;
   tile_of_block(a.reg, a.nreg, a.tile_w, a.tile_h, x0, y0, tw, th);
   const DepthSrc src{a.c, a.roi_dev, a.index_base};
-  depth_tile(src, a.n, x0, y0, tw, th, a.out_color, a.out_depth, a.out_pitch, a.vx, a.vy,
+  __shared__ DepthRec s_rec[kPlaceMax];
+  stage_contributors(src, a.n, s_rec);   // a.n <= kDepthPerPass <= kPlaceMax
+  depth_tile(s_rec, a.n, x0, y0, tw, th, a.out_color, a.out_depth, a.out_pitch, a.vx, a.vy,
              a.accumulate != 0);
 }
 

@@ -40,9 +40,45 @@ struct DepthSrc {
 // `accumulate`, the outputs already hold the result of earlier contributors
 // (a previous pass) and are combined under the same rule.
 constexpr int kDepthRows = 4;    // rows per lane per step
-constexpr int kDepthBatch = 4;   // contributors whose loads are in flight together
+constexpr int kDepthBatch = 4;   // covering contributors whose loads are in flight together
+constexpr int kPlaceMax = 64;    // contributors staged in LDS per call
 
-__device__ __forceinline__ void depth_tile(const DepthSrc src, int n, int x0, int y0, int tw,
+typedef const __attribute__((address_space(1))) uint32_t* GlobalU32;
+
+// A contributor as the tile reads it: placement and buffers.
+struct DepthRec {
+  int32_t x, y, w, h;
+  const uint32_t* depth;
+  const uint32_t* color;
+  int64_t pitch;
+};
+
+// Stages contributors [0, n) (n <= kPlaceMax) in LDS: their placements (the
+// host rectangle or the device ROI, clamped to the host size) and buffers.
+// All threads of the workgroup; ends with a barrier.
+__device__ __forceinline__ void stage_contributors(const DepthSrc& src, int n, DepthRec* rec) {
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    const DepthDesc& D = src.d[i];
+    DepthRec r{D.x, D.y, D.w, D.h, D.depth, D.color, D.pitch};
+    if (src.roi_dev) {
+      const int4 q = reinterpret_cast<const int4*>(src.roi_dev)[src.index_base + i];
+      r.x = q.x;
+      r.y = q.y;
+      r.w = max(0, min(q.z, D.w));
+      r.h = max(0, min(q.w, D.h));
+    }
+    if (!D.depth || r.w <= 0 || r.h <= 0) r.w = r.h = 0;
+    rec[i] = r;
+  }
+  __syncthreads();
+}
+
+// `rec`: contributors staged by stage_contributors (n <= kPlaceMax).
+// Per step a wave first finds, from LDS, which contributors cover its rows
+// and the tile's columns (a 64-bit mask), then loads kDepthBatch covering
+// contributors x 4 rows at a time, so the depth loads of a typical step are
+// one round trip; the winner's colour is gathered at the end.
+__device__ __forceinline__ void depth_tile(const DepthRec* rec, int n, int x0, int y0, int tw,
                                            int th, uint32_t* __restrict__ out_color,
                                            uint32_t* __restrict__ out_depth, int64_t out_pitch,
                                            int vx, int vy, bool accumulate) {
@@ -51,59 +87,76 @@ __device__ __forceinline__ void depth_tile(const DepthSrc src, int n, int x0, in
   for (int cx = 0; cx < tw; cx += kWave) {
     const int X = x0 + cx + lane;
     const bool col_ok = cx + lane < tw;
+    const int cx0 = x0 + cx, cx1 = x0 + min(tw, cx + kWave);   // the wave's columns
     for (int r0 = wave * kDepthRows; r0 < th; r0 += kStepRows) {
       const int Y0 = y0 + r0;                       // rows Y0 .. Y0 + 3 (uniform)
       const int nrows = min(kDepthRows, th - r0);
+      // covering contributors of this step (uniform)
+      uint64_t cover = 0;
+      for (int i = 0; i < n; ++i) {
+        const int rx = uniform(rec[i].x), ry = uniform(rec[i].y);
+        const int rw = uniform(rec[i].w), rh = uniform(rec[i].h);
+        if (rw > 0 && rx < cx1 && rx + rw > cx0 && ry < Y0 + nrows && ry + rh > Y0)
+          cover |= 1ull << i;
+      }
+      cover = (uint64_t)uniform64((int64_t)cover);
       uint32_t bd[kDepthRows], pc[kDepthRows];
-      const uint32_t* bc[kDepthRows];
+      int bi[kDepthRows];
 #pragma unroll
       for (int k = 0; k < kDepthRows; ++k) {
         bd[k] = kClearDepth;
         pc[k] = 0;
-        bc[k] = nullptr;
+        bi[k] = -1;
         if (accumulate && col_ok && k < nrows) {
           const int64_t oo = (int64_t)(Y0 + k - vy) * out_pitch + (X - vx);
           bd[k] = out_depth[oo];
           pc[k] = out_color[oo];
         }
       }
-      for (int i0 = 0; i0 < n; i0 += kDepthBatch) {
-        uint32_t dv[kDepthBatch][kDepthRows];
-        const uint32_t* crow[kDepthBatch];   // colour of this lane's pixel in row Y0 - ry
-        int64_t cpitch[kDepthBatch];
+      while (cover) {   // uniform
+        // the next kDepthBatch covering contributors (a slot past the last
+        // one repeats the first and is ignored), then every load of the
+        // batch, then the compares: no branch between the loads
+        int ids[kDepthBatch];
+        bool has[kDepthBatch];
+        const int first = (int)__builtin_ctzll(cover);
 #pragma unroll
         for (int j = 0; j < kDepthBatch; ++j) {
+          has[j] = cover != 0;
+          ids[j] = has[j] ? (int)__builtin_ctzll(cover) : first;
+          cover &= cover - 1;
+        }
+        uint32_t dv[kDepthBatch][kDepthRows];
+        bool ok[kDepthBatch][kDepthRows];
 #pragma unroll
-          for (int k = 0; k < kDepthRows; ++k) dv[j][k] = kClearDepth;
-          crow[j] = nullptr;
-          cpitch[j] = 0;
-          const int i = i0 + j;
-          if (i >= n) continue;
-          const DepthDesc& D = src.d[i];
-          int32_t rx, ry, rw, rh;
-          placement(src.roi_dev, src.index_base + i, D.x, D.y, D.w, D.h, rx, ry, rw, rh);
-          // whole-step rejection (uniform): columns of the tile, rows of the step
-          if (rw <= 0 || rh <= 0 || rx >= x0 + tw || rx + rw <= x0 || ry >= Y0 + nrows ||
-              ry + rh <= Y0)
-            continue;
-          const bool in_col = col_ok && X >= rx && X < rx + rw;
-          const int64_t off0 = (int64_t)(Y0 - ry) * D.pitch + (X - rx);
-          crow[j] = D.color + off0;
-          cpitch[j] = D.pitch;
+        for (int j = 0; j < kDepthBatch; ++j) {
+          const int i = ids[j];
+          const int rx = uniform(rec[i].x), ry = uniform(rec[i].y);
+          const int rw = uniform(rec[i].w), rh = uniform(rec[i].h);
+          // global (not flat) loads: flat ones would also hold up the LDS counter
+          const GlobalU32 dep = (GlobalU32)uniform_ptr(rec[i].depth);
+          const int64_t pitch = uniform64(rec[i].pitch);
+          const bool in_col = has[j] && col_ok && X >= rx && X < rx + rw;
+          const int lo = in_col ? X - rx : 0;   // this lane's column in the contributor
+          // a uniform row address plus the lane's column; a pixel outside
+          // the contributor reads the first pixel of a valid row instead
 #pragma unroll
           for (int k = 0; k < kDepthRows; ++k) {
             const int yy = Y0 + k - ry;           // uniform
-            if (k < nrows && yy >= 0 && yy < rh && in_col)
-              dv[j][k] = D.depth[off0 + (int64_t)k * D.pitch];
+            const bool rok = k < nrows && yy >= 0 && yy < rh;
+            const GlobalU32 row = rok ? dep + (int64_t)yy * pitch : dep;
+            dv[j][k] = row[lo];
+            ok[j][k] = rok && in_col;
           }
         }
+        // ascending indices and a strict "<": ties keep the lower index
 #pragma unroll
         for (int j = 0; j < kDepthBatch; ++j) {
 #pragma unroll
           for (int k = 0; k < kDepthRows; ++k) {
-            if (dv[j][k] < bd[k]) {
+            if (ok[j][k] && dv[j][k] < bd[k]) {
               bd[k] = dv[j][k];
-              bc[k] = crow[j] + (int64_t)k * cpitch[j];
+              bi[k] = ids[j];
             }
           }
         }
@@ -111,11 +164,20 @@ __device__ __forceinline__ void depth_tile(const DepthSrc src, int n, int x0, in
       // gather the winners' colours and store (4-byte accesses, coalesced
       // along the row across the wave)
       if (col_ok) {
+        uint32_t cv[kDepthRows];
+#pragma unroll
+        for (int k = 0; k < kDepthRows; ++k) {
+          cv[k] = pc[k];
+          if (k < nrows && bi[k] >= 0) {
+            const DepthRec& R = rec[bi[k]];
+            cv[k] = ((GlobalU32)R.color)[(int64_t)(Y0 + k - R.y) * R.pitch + (X - R.x)];
+          }
+        }
 #pragma unroll
         for (int k = 0; k < kDepthRows; ++k) {
           if (k >= nrows) continue;
           const int64_t oo = (int64_t)(Y0 + k - vy) * out_pitch + (X - vx);
-          out_color[oo] = bc[k] ? *bc[k] : pc[k];
+          out_color[oo] = cv[k];
           if (out_depth) out_depth[oo] = bd[k];
         }
       }
