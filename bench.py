@@ -91,6 +91,11 @@ class Frame:
 
 
 STAGES = ["roi_detect", "rle_compress", "rle_decompress", "composite_depth"]
+# the kernels each stage launches (one library call per stage)
+STAGE_KERNELS = {"roi_detect": "roi_kernel<0>",
+                 "rle_compress": "rle_clear_kernel + rle_compress_kernel",
+                 "rle_decompress": "rle_decompress_kernel",
+                 "composite_depth": "depth_kernel"}
 
 
 def algorithmic_bytes(frame, rois, stream_sizes):
@@ -436,7 +441,8 @@ def main():
         "hbm_frac_step": step_bytes / ms_step / 1e6 / PEAK_HBM_GBPS,
         "graph_replay_ms_per_step": graph_ms,
         "stages": stages,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBPS,
+        "roofline": {"bound": "hbm", "kernel": f"{dom}: {STAGE_KERNELS[dom]}", "achieved": achieved,
+                     "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS, "traffic": traffic},
         "probe": dict(probe, frac_of_read_probe=achieved / probe["read_GBps"]),
         "wall_s_timed": wall,
