@@ -13,8 +13,10 @@ several copies of every buffer so that the 256 MB Infinity Cache cannot
 serve a step from the previous one.
 
 Prints one JSON line: Mpixel/s of composited input (the sum of the ROI areas
-supplied per frame), the roofline of the dominant kernel (algorithmic bytes
-over its event-timed average duration), and the oracle timed on the host.
+supplied per frame) with each step's five launches replayed as a HIP graph
+(the eager rate is reported beside it), the roofline of the dominant stage
+(algorithmic bytes over its event-timed average duration in an eager run),
+and the oracle timed on the host.
 """
 from __future__ import annotations
 
@@ -145,8 +147,10 @@ def time_stages(frames, steps, warmup, s_obj):
     return total_ms, wall, per
 
 
-def time_graph(frames, steps, s_obj):
-    """The same steps captured as HIP graphs (one per frame copy) and replayed."""
+def time_graph(frames, steps, warmup, s_obj):
+    """The same steps captured as HIP graphs (one per frame copy, holding the
+    step's five launches) and replayed: `warmup` untimed replays, then
+    `steps` timed ones between a synchronize on each side."""
     graphs = []
     for f in frames:
         g = torch.cuda.CUDAGraph()
@@ -155,17 +159,18 @@ def time_graph(frames, steps, s_obj):
                 f.stage(k, torch.cuda.current_stream().cuda_stream)
         graphs.append(g)
     torch.cuda.synchronize()
-    for g in graphs:
-        g.replay()
+    for i in range(max(warmup, len(graphs))):
+        graphs[i % len(graphs)].replay()
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
     t0.record()
     for i in range(steps):
         graphs[i % len(graphs)].replay()
     t1.record()
     torch.cuda.synchronize()
-    return t0.elapsed_time(t1)
+    return t0.elapsed_time(t1), time.perf_counter() - w0
 
 
 def bandwidth_probe(dev, nbytes=2 << 30, reps=10):
@@ -411,7 +416,8 @@ def main():
         stages[name] = {"us": float(stage_ms[k] * 1e3), "bytes": int(abytes[name]),
                         "GBps": float(abytes[name] / stage_ms[k] / 1e6)}
     dom = max(STAGES, key=lambda n: stages[n]["us"])
-    graph_ms = time_graph(frames, args.steps, s_obj) / args.steps
+    graph_total, graph_wall = time_graph(frames, args.steps, args.warmup, s_obj)
+    graph_ms = graph_total / args.steps
     probe = bandwidth_probe(dev)
     step_bytes = sum(abytes.values())
     achieved = stages[dom]["GBps"]
@@ -421,12 +427,12 @@ def main():
         traffic = float(t["bytes_per_launch"])
     result = {
         "metric": METRIC,
-        "value": roi_px / (ms_step * 1e3),
+        "value": roi_px / (graph_ms * 1e3),
         "unit": "Mpixel/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": graph_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -437,15 +443,19 @@ def main():
                    "contributors": 16, "width": 1920, "height": 1080,
                    "roi_area_fraction": "0.25-0.35", "schedule": "binary_swap(16)",
                    "composited_input_px_per_step": roi_px, "buffer_copies": args.copies},
-        "hbm_GBps_step": step_bytes / ms_step / 1e6,
-        "hbm_frac_step": step_bytes / ms_step / 1e6 / PEAK_HBM_GBPS,
-        "graph_replay_ms_per_step": graph_ms,
+        "timing": "value and ms_per_step: the step's five launches replayed as a HIP graph; "
+                  "stages and roofline: per-stage events of the same steps run eagerly",
+        "eager_ms_per_step": ms_step,
+        "eager_value": roi_px / (ms_step * 1e3),
+        "hbm_GBps_step": step_bytes / graph_ms / 1e6,
+        "hbm_frac_step": step_bytes / graph_ms / 1e6 / PEAK_HBM_GBPS,
         "stages": stages,
         "roofline": {"bound": "hbm", "kernel": f"{dom}: {STAGE_KERNELS[dom]}", "achieved": achieved,
                      "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS, "traffic": traffic},
         "probe": dict(probe, frac_of_read_probe=achieved / probe["read_GBps"]),
-        "wall_s_timed": wall,
+        "wall_s_timed": graph_wall,
+        "wall_s_timed_eager": wall,
     }
     if not args.no_extras:
         log("extras: over 64x3840x2160 fp32/fp16, backward 32x1024x1024, batch of 256 jobs")
