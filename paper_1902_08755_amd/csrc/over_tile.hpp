@@ -56,11 +56,14 @@ __device__ __forceinline__ bool tile_misses(int rx, int ry, int rw, int rh, int 
 }
 
 // Blends layers [j0, j1) of `d` (back-to-front positions) at pixel (X, Y)
-// onto acc.
+// onto acc. The loads of a batch are unconditional, so that no branch
+// separates them: a layer that misses the tile (a uniform test) reads from
+// `safe` (any readable address, e.g. the output), and a lane outside a
+// layer reads the layer's first pixel; both results are discarded.
 template <int FMT>
 __device__ __forceinline__ f32x4 over_range(const OverDesc* __restrict__ d, int j0, int j1,
                                             int X, int Y, int x0, int y0, int tw, int th,
-                                            f32x4 acc) {
+                                            const void* safe, f32x4 acc) {
   constexpr int B = over_batch<FMT>();
   typedef typename RawPx<FMT>::type Raw;
   for (int jb = j0; jb < j1; jb += B) {
@@ -68,15 +71,12 @@ __device__ __forceinline__ f32x4 over_range(const OverDesc* __restrict__ d, int 
     bool cov[B];
 #pragma unroll
     for (int k = 0; k < B; ++k) {
-      L[k] = Raw{0, 0, 0, 0};
-      cov[k] = false;
-      const int j = jb + k;
-      if (j >= j1) continue;
+      const int j = min(jb + k, j1 - 1);
       const OverDesc& D = d[j];
-      if (tile_misses(D.x, D.y, D.w, D.h, x0, y0, tw, th)) continue;
-      if (X < D.x || X >= D.x + D.w || Y < D.y || Y >= D.y + D.h) continue;
-      cov[k] = true;
-      L[k] = ld_raw<FMT>(D.color, (int64_t)(Y - D.y) * D.pitch + (X - D.x));
+      const bool hit = jb + k < j1 && !tile_misses(D.x, D.y, D.w, D.h, x0, y0, tw, th);
+      cov[k] = hit && X >= D.x && X < D.x + D.w && Y >= D.y && Y < D.y + D.h;
+      const void* base = hit ? D.color : safe;
+      L[k] = ld_raw<FMT>(base, cov[k] ? (int64_t)(Y - D.y) * D.pitch + (X - D.x) : 0);
     }
 #pragma unroll
     for (int k = 0; k < B; ++k)
@@ -98,7 +98,7 @@ __device__ __forceinline__ void over_tile_seq(const OverDesc* __restrict__ d, in
     const int X = x0 + c, Y = y0 + r;
     f32x4* o = reinterpret_cast<f32x4*>(out) + ((int64_t)(Y - vy) * out_pitch + (X - vx));
     f32x4 acc = accumulate ? *o : f32x4{0.f, 0.f, 0.f, 0.f};
-    acc = over_range<FMT>(d, 0, n, X, Y, x0, y0, tw, th, acc);
+    acc = over_range<FMT>(d, 0, n, X, Y, x0, y0, tw, th, out, acc);
     *o = acc;
   }
 }
@@ -124,7 +124,7 @@ __device__ __forceinline__ void over_tile_tree(const OverDesc* __restrict__ d,
     const int c = p - r * tw;
     const int X = x0 + c, Y = y0 + r;
     for (int g = 0; g < groups; ++g) {
-      f32x4 carry = over_range<FMT>(d, gb[g], gb[g + 1], X, Y, x0, y0, tw, th,
+      f32x4 carry = over_range<FMT>(d, gb[g], gb[g + 1], X, Y, x0, y0, tw, th, out,
                                     f32x4{0.f, 0.f, 0.f, 0.f});
       int l = 0;
       for (; (g >> l) & 1; ++l) carry = over_op(carry, lvl[l][threadIdx.x]);
