@@ -59,6 +59,7 @@ struct BatchArgs {
 __global__ __launch_bounds__(kThreads) void batch_kernel(const BatchArgs a) {
   __shared__ int s_item;
   __shared__ DepthRec s_rec[kPlaceMax];   // contributors of the current depth job
+  __shared__ OverDesc s_od[kOverStage];   // layers of the current over job
   const int tid = threadIdx.x;
   while (true) {
     if (tid == 0)
@@ -89,15 +90,22 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const BatchArgs a) {
       }
       continue;
     }
+    // an over job's layer descriptors go to LDS when they fit
+    const int on = uniform(J.n);
+    const OverDesc* od = a.odesc + J.desc_off;
+    if (on <= kOverStage) {
+      stage_layers(od, on, s_od);
+      od = s_od;
+    }
     for (int tile = uniform(I.tile0); tile < t1; ++tile) {
       const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
       const int x0 = J.vx + tx * J.tile_w, y0 = J.vy + ty * J.tile_h;
       const int tw = min(J.tile_w, J.vx + J.vw - x0), th = min(J.tile_h, J.vy + J.vh - y0);
       if (J.fmt == CMP_RGBA32F) {
-        over_tile_seq<CMP_RGBA32F>(a.odesc + J.desc_off, J.n, x0, y0, tw, th, (float*)J.out_color,
+        over_tile_seq<CMP_RGBA32F>(od, J.n, x0, y0, tw, th, (float*)J.out_color,
                                    J.out_pitch, J.vx, J.vy, false);
       } else {
-        over_tile_seq<CMP_RGBA16F>(a.odesc + J.desc_off, J.n, x0, y0, tw, th, (float*)J.out_color,
+        over_tile_seq<CMP_RGBA16F>(od, J.n, x0, y0, tw, th, (float*)J.out_color,
                                    J.out_pitch, J.vx, J.vy, false);
       }
     }

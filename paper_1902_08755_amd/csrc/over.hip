@@ -8,6 +8,7 @@
 namespace cmp {
 
 constexpr int kOverPerPass = 64;
+static_assert(kOverPerPass <= kOverStage, "a pass's layers are staged in LDS");
 
 struct OverArgs {
   OverDesc c[kOverPerPass];      // back to front
@@ -42,7 +43,9 @@ template <int FMT>
 __global__ __launch_bounds__(kThreads) void over_kernel(const OverArgs a) {
   int x0, y0, tw, th;
   region_tile(a.reg, a.nreg, a.tile_w, a.tile_h, x0, y0, tw, th);
-  over_tile_seq<FMT>(a.c, a.n, x0, y0, tw, th, a.out, a.out_pitch, a.vx, a.vy,
+  __shared__ OverDesc s_d[kOverStage];
+  stage_layers(a.c, a.n, s_d);   // a.n <= kOverPerPass == kOverStage
+  over_tile_seq<FMT>(s_d, a.n, x0, y0, tw, th, a.out, a.out_pitch, a.vx, a.vy,
                      a.accumulate != 0);
 }
 
@@ -50,7 +53,9 @@ template <int FMT>
 __global__ __launch_bounds__(kThreads) void over_tree_kernel(const OverArgs a) {
   int x0, y0, tw, th;
   region_tile(a.reg, a.nreg, a.tile_w, a.tile_h, x0, y0, tw, th);
-  over_tile_tree<FMT>(a.c, a.gb, a.groups, x0, y0, tw, th, a.out, a.out_pitch, a.vx, a.vy);
+  __shared__ OverDesc s_d[kOverStage];
+  stage_layers(a.c, a.n, s_d);
+  over_tile_tree<FMT>(s_d, a.gb, a.groups, x0, y0, tw, th, a.out, a.out_pitch, a.vx, a.vy);
 }
 
 // ------------------------------------------------------------- backward

@@ -32,7 +32,8 @@ struct RawPx<CMP_RGBA16F> { typedef f16x4 type; };
 
 template <int FMT>
 __device__ __forceinline__ typename RawPx<FMT>::type ld_raw(const void* base, int64_t px) {
-  return reinterpret_cast<const typename RawPx<FMT>::type*>(base)[px];
+  typedef const __attribute__((address_space(1))) typename RawPx<FMT>::type* GPtr;
+  return ((GPtr)base)[px];
 }
 __device__ __forceinline__ f32x4 widen(f32x4 v) { return v; }
 __device__ __forceinline__ f32x4 widen(f16x4 h) {
@@ -55,33 +56,68 @@ __device__ __forceinline__ bool tile_misses(int rx, int ry, int rw, int rh, int 
   return rw <= 0 || rh <= 0 || rx >= x0 + tw || rx + rw <= x0 || ry >= y0 + th || ry + rh <= y0;
 }
 
-// Blends layers [j0, j1) of `d` (back-to-front positions) at pixel (X, Y)
-// onto acc. The loads of a batch are unconditional, so that no branch
-// separates them: a layer that misses the tile (a uniform test) reads from
-// `safe` (any readable address, e.g. the output), and a lane outside a
+// Copies the descriptors of layers [0, n) (n <= 64) to LDS: a tile reads a
+// layer's placement and buffer from there (uniform LDS reads), not from the
+// kernel arguments or the batch workspace. All threads; ends with a barrier.
+constexpr int kOverStage = 64;
+__device__ __forceinline__ void stage_layers(const OverDesc* __restrict__ src, int n,
+                                             OverDesc* s_d) {
+  for (int i = threadIdx.x; i < n; i += kThreads) s_d[i] = src[i];
+  __syncthreads();
+}
+
+// Layers [c0, c1) (c1 - c0 <= 64) that reach the tile, as a bit mask
+// (bit i: layer c0 + i). Uniform.
+__device__ __forceinline__ uint64_t tile_hits(const OverDesc* __restrict__ d, int c0, int c1,
+                                              int x0, int y0, int tw, int th) {
+  uint64_t m = 0;
+  for (int j = c0; j < c1; ++j) {
+    const OverDesc& D = d[j];
+    if (!tile_misses(uniform(D.x), uniform(D.y), uniform(D.w), uniform(D.h), x0, y0, tw, th))
+      m |= 1ull << (j - c0);
+  }
+  return (uint64_t)uniform64((int64_t)m);
+}
+
+// Blends, in increasing order, the layers base + i for the set bits i of
+// `hits` (layers that reach the tile) at pixel (X, Y) onto acc. A batch's
+// loads are unconditional, so that no branch separates them: a slot past
+// the last layer repeats the batch's first layer, and a lane outside a
 // layer reads the layer's first pixel; both results are discarded.
 template <int FMT>
-__device__ __forceinline__ f32x4 over_range(const OverDesc* __restrict__ d, int j0, int j1,
-                                            int X, int Y, int x0, int y0, int tw, int th,
-                                            const void* safe, f32x4 acc) {
+__device__ __forceinline__ f32x4 over_hits(const OverDesc* __restrict__ d, int base,
+                                           uint64_t hits, int X, int Y, f32x4 acc) {
   constexpr int B = over_batch<FMT>();
   typedef typename RawPx<FMT>::type Raw;
-  for (int jb = j0; jb < j1; jb += B) {
+  while (hits) {   // uniform
     Raw L[B];
     bool cov[B];
+    const int first = (int)__builtin_ctzll(hits);
 #pragma unroll
     for (int k = 0; k < B; ++k) {
-      const int j = min(jb + k, j1 - 1);
-      const OverDesc& D = d[j];
-      const bool hit = jb + k < j1 && !tile_misses(D.x, D.y, D.w, D.h, x0, y0, tw, th);
-      cov[k] = hit && X >= D.x && X < D.x + D.w && Y >= D.y && Y < D.y + D.h;
-      const void* base = hit ? D.color : safe;
-      L[k] = ld_raw<FMT>(base, cov[k] ? (int64_t)(Y - D.y) * D.pitch + (X - D.x) : 0);
+      const bool has = hits != 0;
+      const OverDesc& D = d[base + (has ? (int)__builtin_ctzll(hits) : first)];
+      hits &= hits - 1;
+      const int dx = uniform(D.x), dy = uniform(D.y), dw = uniform(D.w), dh = uniform(D.h);
+      const void* color = uniform_ptr(D.color);
+      const int64_t pitch = uniform64(D.pitch);
+      cov[k] = has && X >= dx && X < dx + dw && Y >= dy && Y < dy + dh;
+      L[k] = ld_raw<FMT>(color, cov[k] ? (int64_t)(Y - dy) * pitch + (X - dx) : 0);
     }
 #pragma unroll
     for (int k = 0; k < B; ++k)
       if (cov[k]) acc = over_op(widen(L[k]), acc);
   }
+  return acc;
+}
+
+// Layers [j0, j1) at pixel (X, Y) onto acc, 64 at a time.
+template <int FMT>
+__device__ __forceinline__ f32x4 over_range(const OverDesc* __restrict__ d, int j0, int j1,
+                                            int X, int Y, int x0, int y0, int tw, int th,
+                                            f32x4 acc) {
+  for (int c0 = j0; c0 < j1; c0 += 64)
+    acc = over_hits<FMT>(d, c0, tile_hits(d, c0, min(j1, c0 + 64), x0, y0, tw, th), X, Y, acc);
   return acc;
 }
 
@@ -92,13 +128,16 @@ __device__ __forceinline__ void over_tile_seq(const OverDesc* __restrict__ d, in
                                               int64_t out_pitch, int vx, int vy,
                                               bool accumulate) {
   const int np = tw * th;
+  // the layers that reach the tile, found once for all its pixels (n <= 64)
+  const uint64_t hits = n <= 64 ? tile_hits(d, 0, n, x0, y0, tw, th) : 0;
   for (int p = threadIdx.x; p < np; p += kThreads) {
     const int r = p / tw;
     const int c = p - r * tw;
     const int X = x0 + c, Y = y0 + r;
     f32x4* o = reinterpret_cast<f32x4*>(out) + ((int64_t)(Y - vy) * out_pitch + (X - vx));
     f32x4 acc = accumulate ? *o : f32x4{0.f, 0.f, 0.f, 0.f};
-    acc = over_range<FMT>(d, 0, n, X, Y, x0, y0, tw, th, out, acc);
+    acc = n <= 64 ? over_hits<FMT>(d, 0, hits, X, Y, acc)
+                  : over_range<FMT>(d, 0, n, X, Y, x0, y0, tw, th, acc);
     *o = acc;
   }
 }
@@ -119,13 +158,16 @@ __device__ __forceinline__ void over_tile_tree(const OverDesc* __restrict__ d,
   const int np = tw * th;
   int levels = 0;
   while ((1 << levels) < groups) ++levels;
+  // n <= 64 layers in all (one pass): the tile's layers found once
+  const uint64_t hits = tile_hits(d, 0, gb[groups], x0, y0, tw, th);
   for (int p = threadIdx.x; p < np; p += kThreads) {
     const int r = p / tw;
     const int c = p - r * tw;
     const int X = x0 + c, Y = y0 + r;
     for (int g = 0; g < groups; ++g) {
-      f32x4 carry = over_range<FMT>(d, gb[g], gb[g + 1], X, Y, x0, y0, tw, th, out,
-                                    f32x4{0.f, 0.f, 0.f, 0.f});
+      const int j0 = gb[g], j1 = gb[g + 1];
+      const uint64_t span = (j1 - j0 >= 64 ? ~0ull : ((1ull << (j1 - j0)) - 1ull)) << j0;
+      f32x4 carry = over_hits<FMT>(d, 0, hits & span, X, Y, f32x4{0.f, 0.f, 0.f, 0.f});
       int l = 0;
       for (; (g >> l) & 1; ++l) carry = over_op(carry, lvl[l][threadIdx.x]);
       lvl[l][threadIdx.x] = carry;
