@@ -13,10 +13,11 @@ several copies of every buffer so that the 256 MB Infinity Cache cannot
 serve a step from the previous one.
 
 Prints one JSON line: Mpixel/s of composited input (the sum of the ROI areas
-supplied per frame) with each step's five launches replayed as a HIP graph
-(the eager rate is reported beside it), the roofline of the dominant stage
-(algorithmic bytes over its event-timed average duration in an eager run),
-and the oracle timed on the host.
+supplied per frame) with frames composited asynchronously, two in flight on
+two streams (one frame at a time, as a HIP graph and eagerly, is reported
+beside it), the roofline of the dominant stage (algorithmic bytes over its
+event-timed average duration, one frame at a time), and the oracle timed on
+the host.
 """
 from __future__ import annotations
 
@@ -145,6 +146,42 @@ def time_stages(frames, steps, warmup, s_obj):
     total_ms = t0.elapsed_time(t1)
     per = np.array([[ev[i][k].elapsed_time(ev[i][k + 1]) for k in range(4)] for i in range(steps)])
     return total_ms, wall, per
+
+
+def time_pipelined(frames, steps, warmup, s_obj, in_flight=2):
+    """Frames composited asynchronously (the thesis's pipelined compositing of
+    consecutive frames, Section 5.4): step i runs the whole chain for buffer
+    copy i mod 4 on stream i mod in_flight, so `in_flight` frames overlap
+    (a ROI scan or a compositing pass of one frame next to the RLE kernels
+    of another). Each copy's steps stay in order on their stream. Returns
+    the milliseconds and wall seconds of `steps` steps between a
+    synchronize on each side."""
+    streams = [torch.cuda.Stream() for _ in range(in_flight)]
+    nf = len(frames)
+
+    def run(count):
+        for i in range(count):
+            st = streams[i % in_flight].cuda_stream
+            f = frames[i % nf]
+            for k in range(4):
+                f.stage(k, st)
+
+    run(max(warmup, nf))
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    t0.record(s_obj)
+    for st in streams:
+        st.wait_event(t0)
+    run(steps)
+    for st in streams:
+        e = torch.cuda.Event()
+        e.record(st)
+        s_obj.wait_event(e)
+    t1.record(s_obj)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1), time.perf_counter() - w0
 
 
 def time_graph(frames, steps, warmup, s_obj):
@@ -418,6 +455,8 @@ def main():
     dom = max(STAGES, key=lambda n: stages[n]["us"])
     graph_total, graph_wall = time_graph(frames, args.steps, args.warmup, s_obj)
     graph_ms = graph_total / args.steps
+    pipe_total, pipe_wall = time_pipelined(frames, args.steps, args.warmup, s_obj)
+    pipe_ms = pipe_total / args.steps
     probe = bandwidth_probe(dev)
     step_bytes = sum(abytes.values())
     achieved = stages[dom]["GBps"]
@@ -427,12 +466,12 @@ def main():
         traffic = float(t["bytes_per_launch"])
     result = {
         "metric": METRIC,
-        "value": roi_px / (graph_ms * 1e3),
+        "value": roi_px / (pipe_ms * 1e3),
         "unit": "Mpixel/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": graph_ms,
+        "ms_per_step": pipe_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -443,18 +482,22 @@ def main():
                    "contributors": 16, "width": 1920, "height": 1080,
                    "roi_area_fraction": "0.25-0.35", "schedule": "binary_swap(16)",
                    "composited_input_px_per_step": roi_px, "buffer_copies": args.copies},
-        "timing": "value and ms_per_step: the step's five launches replayed as a HIP graph; "
-                  "stages and roofline: per-stage events of the same steps run eagerly",
+        "timing": "value and ms_per_step: frames composited asynchronously, 2 in flight (each "
+                  "frame's whole chain on one of 2 streams); graph: one frame at a time, its five "
+                  "launches replayed as a HIP graph; stages and roofline: per-stage events of one "
+                  "frame at a time, eager",
+        "frames_in_flight": 2,
+        "graph_ms_per_step": graph_ms,
         "eager_ms_per_step": ms_step,
-        "eager_value": roi_px / (ms_step * 1e3),
-        "hbm_GBps_step": step_bytes / graph_ms / 1e6,
-        "hbm_frac_step": step_bytes / graph_ms / 1e6 / PEAK_HBM_GBPS,
+        "hbm_GBps_step": step_bytes / pipe_ms / 1e6,
+        "hbm_frac_step": step_bytes / pipe_ms / 1e6 / PEAK_HBM_GBPS,
         "stages": stages,
         "roofline": {"bound": "hbm", "kernel": f"{dom}: {STAGE_KERNELS[dom]}", "achieved": achieved,
                      "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS, "traffic": traffic},
         "probe": dict(probe, frac_of_read_probe=achieved / probe["read_GBps"]),
-        "wall_s_timed": graph_wall,
+        "wall_s_timed": pipe_wall,
+        "wall_s_timed_graph": graph_wall,
         "wall_s_timed_eager": wall,
     }
     if not args.no_extras:
