@@ -321,7 +321,9 @@ def workspace(tag: str, nbytes: int, device=None) -> torch.Tensor:
 
 
 def roi_detect(images: Sequence, fmt: int = RGBA8, roi_out=None, ws=None, stream=None):
-    """Automatic ROI detection (cmp_roi_detect); returns an int32 (n, 4) tensor."""
+    """Automatic ROI detection (cmp_roi_detect); returns an int32 (n, 4) tensor.
+    Without `ws` the call uses a workspace shared by all calls on the device:
+    calls that may overlap (on other streams) must each pass their own."""
     n = len(images)
     arr = _images(images, "rgba" if fmt != RGBA8 else "u32")
     if roi_out is None:

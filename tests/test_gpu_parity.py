@@ -582,6 +582,48 @@ def test_ramp_pipeline_full_size():
     assert (ref_c == full_c).all() and (ref_d == full_d).all()
 
 
+def test_two_frames_in_flight_match_one_at_a_time():
+    """The benchmark's asynchronous mode: two frames' whole chains (ROI, RLE
+    compress, decompress, depth compositing) on two streams at once give the
+    same streams and composites as running them one after the other."""
+    note("two frames in flight")
+    frames = [synth.depth_ramps_full(seed=s, n=16, W=1920, H=1080, device=DEV) for s in (2, 3)]
+
+    def chain(wl, stream):
+        with torch.cuda.stream(stream):
+            # calls that may overlap need their own ROI workspace
+            ws = torch.zeros(1 << 16, dtype=torch.uint8, device=DEV)
+            roi = cmp.roi_detect(wl.images, ws=ws)
+            batch = cmp.RleBatch(wl.images, roi_dev=roi)
+            streams, sizes = batch.run()
+            blocks = [cmp.Image(torch.zeros((1080, 1920), dtype=torch.int32, device=DEV),
+                                torch.zeros((1080, 1920), dtype=torch.int32, device=DEV),
+                                (0, 0, 1920, 1080)) for _ in range(16)]
+            ro, st = cmp.rle_decompress(streams, blocks)
+            placed = [cmp.Image(b.color, b.depth, (0, 0, 1920, 1080)) for b in blocks]
+            oc, od = cmp.composite_depth(placed, wl.viewport, roi_dev=ro,
+                                         schedule=("binary_swap", 16))
+        return roi, streams, sizes, st, oc, od
+
+    main = torch.cuda.current_stream()
+    seq = [chain(wl, main) for wl in frames]
+    torch.cuda.synchronize()
+    side = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for st in side:
+        st.wait_stream(main)
+    par = [chain(wl, st) for wl, st in zip(frames, side)]
+    for st in side:
+        main.wait_stream(st)
+    torch.cuda.synchronize()
+    for a, b in zip(seq, par):
+        assert torch.equal(a[0], b[0])
+        assert torch.equal(a[2], b[2]) and (a[3] == 0).all() and (b[3] == 0).all()
+        for k in range(16):
+            n = int(a[2][k])
+            assert torch.equal(a[1][k][:n], b[1][k][:n]), k
+        assert torch.equal(a[4], b[4]) and torch.equal(a[5], b[5])
+
+
 def test_rle_swizzled_streams():
     """Bit-swizzled colour planes: byte-identical streams and round trips."""
     wl = synth.depth_ramps_full(seed=2, n=4, W=640, H=360, device=DEV)
