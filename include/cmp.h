@@ -213,7 +213,8 @@ cmp_status cmp_assemble_pixels(const cmp_image* in, int32_t n, const int32_t* of
  *   roi_out_dev  device int32[n][4]: image-local (x, y, w, h); an image
  *                without data gives (0, 0, 0, 0).
  *   workspace    device, >= cmp_roi_workspace_size(imgs, n) bytes, zero-filled
- *                before its first use; every call leaves it zeroed again.
+ *                before its first use (per-image tickets, then a partial box
+                per workgroup); every call leaves the tickets zeroed again.
  * Calls that share a workspace must not overlap. n <= 64.
  * Errors: CMP_EINVAL, CMP_ENOSPC (workspace), CMP_EHIP.
  */

@@ -5,11 +5,14 @@
 // band of rows with 16-byte loads (4 depth or RGBA8 pixels, 2 RGBA16F pixels
 // or 1 RGBA32F pixel per load, several in flight per lane), keeps per-lane
 // min/max of the data pixels' columns and rows, reduces them across the wave
-// and the workgroup, and folds the box into the image's accumulator with
-// device-scope atomic maxima. The last workgroup of an image (counted with an
-// atomic ticket) turns the accumulator into the rectangle and clears it and
-// the ticket, so the workspace is ready for the next call. No fence is
-// needed: every access to the shared words is a device-scope atomic.
+// and the workgroup, and stores the workgroup's box in a slot of its own.
+// The last workgroup of an image (counted with an atomic ticket, one per
+// image on its own cache line) folds the image's slots into the rectangle and
+// clears the ticket, so the workspace is ready for the next call. One
+// read-modify-write per workgroup: atomics on a shared line are serialised,
+// and per-workgroup atomic maxima on a few shared words cost several
+// microseconds at the end of the launch. No fence is needed: every access to
+// the shared words is a device-scope atomic.
 #include <string.h>
 
 #include "cmp_internal.hpp"
@@ -18,8 +21,10 @@ namespace cmp {
 
 constexpr int kRoiMax = 64;
 constexpr int kRoiBatch = 8;
-// workspace: int32 tickets[64] (256 bytes), then int32 accumulators[64][4]
-constexpr size_t kRoiWorkspace = 256 + 64 * 16;
+// workspace: one int32 ticket per image, each on its own 128-byte line
+// (8 KiB), then one int32[4] partial box per workgroup
+constexpr int kTicketStride = 32;
+constexpr size_t kRoiTickets = (size_t)kRoiMax * kTicketStride * 4;
 
 struct RoiImg {
   const void* color;
@@ -35,8 +40,8 @@ struct RoiImg {
 struct RoiArgs {
   RoiImg im[kRoiMax];
   int32_t* roi_out;
-  int32_t* ticket;    // workspace: int32[64] tickets
-  int32_t* acc;       // workspace: int32[64][4] box accumulators
+  int32_t* ticket;    // workspace: a ticket per image, kTicketStride words apart
+  int4* part;         // workspace: a partial box per workgroup
   int32_t n;
   int32_t mode;       // 0 depth, 1 RGBA8 colour, 2 RGBA32F, 3 RGBA16F
 };
@@ -159,6 +164,7 @@ __global__ __launch_bounds__(kThreads) void roi_kernel(const RoiArgs a) {
     }
   }
   __shared__ int4 red[kThreads / kWave];
+  __shared__ bool s_last;
   minx = wave_min(minx);
   miny = wave_min(miny);
   maxx = wave_max(maxx);
@@ -175,43 +181,80 @@ __global__ __launch_bounds__(kThreads) void roi_kernel(const RoiArgs a) {
       b.z = max(b.z, red[w].z);
       b.w = max(b.w, red[w].w);
     }
-    // fold into the image's accumulator with device-scope atomic maxima; the
-    // encoding (INT_MAX - min, max + 1) makes a zeroed accumulator the empty
-    // box. No fence: the atomics complete (s_waitcnt) before the ticket.
-    int* acc = a.acc + 4 * s;
-    if (b.z >= 0) {
-      __hip_atomic_fetch_max(&acc[0], 0x7FFFFFFF - b.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_max(&acc[1], 0x7FFFFFFF - b.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_max(&acc[2], b.z + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_max(&acc[3], b.w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    // the workgroup's box goes to its own slot, then the image's ticket is
+    // taken; the slot stores complete (s_waitcnt) before the ticket, so the
+    // image's last workgroup sees every slot. Device-scope atomic stores and
+    // loads, no fence; one read-modify-write per workgroup.
+    int* slot = reinterpret_cast<int*>(a.part + blk);
+    __hip_atomic_store(&slot[0], b.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&slot[1], b.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&slot[2], b.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&slot[3], b.w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    const int t = __hip_atomic_fetch_add(&a.ticket[s], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (t == I.nwg - 1) {   // the image's last workgroup
-      const int ax = __hip_atomic_load(&acc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int ay = __hip_atomic_load(&acc[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int az = __hip_atomic_load(&acc[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int aw = __hip_atomic_load(&acc[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      int4 r = int4{0, 0, 0, 0};
-      if (az > 0) {
-        const int x0 = 0x7FFFFFFF - ax, y0 = 0x7FFFFFFF - ay;
-        r = int4{x0, y0, az - x0, aw - y0};
+    const int t = __hip_atomic_fetch_add(&a.ticket[s * kTicketStride], 1, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    s_last = t == I.nwg - 1;
+  }
+  __syncthreads();
+  if (s_last) {   // the image's last workgroup folds the image's slots
+    int4 r{0x7FFFFFFF, 0x7FFFFFFF, -1, -1};
+#pragma unroll 4
+    for (int i = threadIdx.x; i < I.nwg; i += kThreads) {
+      const int* slot = reinterpret_cast<const int*>(a.part + I.wg_begin + i);
+      r.x = min(r.x, __hip_atomic_load(&slot[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      r.y = min(r.y, __hip_atomic_load(&slot[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      r.z = max(r.z, __hip_atomic_load(&slot[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      r.w = max(r.w, __hip_atomic_load(&slot[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+    r.x = wave_min(r.x);
+    r.y = wave_min(r.y);
+    r.z = wave_max(r.z);
+    r.w = wave_max(r.w);
+    __syncthreads();   // red[] is reused
+    if (lane == 0) red[wave] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int w = 1; w < kThreads / kWave; ++w) {
+        r.x = min(r.x, red[w].x);
+        r.y = min(r.y, red[w].y);
+        r.z = max(r.z, red[w].z);
+        r.w = max(r.w, red[w].w);
       }
-      reinterpret_cast<int4*>(a.roi_out)[s] = r;
-      for (int k = 0; k < 4; ++k)
-        __hip_atomic_store(&acc[k], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&a.ticket[s], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int4 box{0, 0, 0, 0};
+      if (r.z >= 0) box = int4{r.x, r.y, r.z - r.x + 1, r.w - r.y + 1};
+      reinterpret_cast<int4*>(a.roi_out)[s] = box;
+      __hip_atomic_store(&a.ticket[s * kTicketStride], 0, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
 
-// Rows per workgroup: about 256 KiB of reads per workgroup.
+// Rows per workgroup: about 128 KiB of reads per workgroup, and at most
+// kRoiSlotsMax workgroups per image (the slots its last workgroup folds).
+constexpr int kRoiSlotsMax = 1024;
 static int roi_rows(const cmp_image& I, int bpp) {
   const int64_t row_bytes = (int64_t)(I.roi.w > 0 ? I.roi.w : 1) * bpp;
-  int64_t r = (256 * 1024 + row_bytes - 1) / row_bytes;
+  int64_t r = (128 * 1024 + row_bytes - 1) / row_bytes;
+  r = std::max<int64_t>(r, ((int64_t)I.roi.h + kRoiSlotsMax - 1) / kRoiSlotsMax);
   if (r < 1) r = 1;
   if (r > I.roi.h) r = I.roi.h > 0 ? I.roi.h : 1;
   return (int)r;
+}
+
+// Workgroups of a launch over images [0, n): an empty image takes one.
+static int64_t roi_workgroups(const cmp_image* imgs, int n, int bpp) {
+  int64_t wg = 0;
+  for (int i = 0; i < n; ++i) {
+    const cmp_image& I = imgs[i];
+    if (!rect_valid(I.roi) || rect_empty(I.roi)) {
+      wg += 1;
+      continue;
+    }
+    const int rows = roi_rows(I, bpp);
+    wg += (I.roi.h + rows - 1) / rows;
+  }
+  return wg;
 }
 
 static int roi_bpp(cmp_format fmt) { return fmt == CMP_RGBA32F ? 16 : fmt == CMP_RGBA16F ? 8 : 4; }
@@ -292,7 +335,8 @@ using namespace cmp;
 
 extern "C" size_t cmp_roi_workspace_size(const cmp_image* imgs, int32_t n) {
   if (n < 0 || (n > 0 && !imgs)) return 0;
-  return kRoiWorkspace;
+  // 16-byte pixels give the most workgroups
+  return kRoiTickets + sizeof(int4) * (size_t)roi_workgroups(imgs, n, 16);
 }
 
 extern "C" cmp_status cmp_roi_detect(const cmp_image* imgs, int32_t n, cmp_format fmt,
@@ -334,14 +378,14 @@ extern "C" cmp_status cmp_roi_detect(const cmp_image* imgs, int32_t n, cmp_forma
     wg += nwg;
   }
   CMP_REQUIRE(wg < (1 << 24), "too many workgroups");
-  const size_t need = kRoiWorkspace;
+  const size_t need = kRoiTickets + sizeof(int4) * (size_t)wg;
   if (ws_bytes < need) {
     set_error("workspace of %zu bytes is smaller than %zu", ws_bytes, need);
     return CMP_ENOSPC;
   }
   a.roi_out = roi_out_dev;
   a.ticket = (int32_t*)workspace;
-  a.acc = (int32_t*)((char*)workspace + 256);
+  a.part = (int4*)((char*)workspace + kRoiTickets);
   a.n = n;
   a.mode = mode;
   hipStream_t s = (hipStream_t)stream;

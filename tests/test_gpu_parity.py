@@ -592,7 +592,8 @@ def test_two_frames_in_flight_match_one_at_a_time():
     def chain(wl, stream):
         with torch.cuda.stream(stream):
             # calls that may overlap need their own ROI workspace
-            ws = torch.zeros(1 << 16, dtype=torch.uint8, device=DEV)
+            need = cmp.lib().cmp_roi_workspace_size(cmp._images(wl.images, "u32"), len(wl.images))
+            ws = torch.zeros(need, dtype=torch.uint8, device=DEV)
             roi = cmp.roi_detect(wl.images, ws=ws)
             batch = cmp.RleBatch(wl.images, roi_dev=roi)
             streams, sizes = batch.run()
