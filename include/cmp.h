@@ -279,6 +279,14 @@ size_t cmp_rle_max_size(int32_t w, int32_t h, int32_t nplanes);
  *   workspace     device, >= cmp_rle_workspace_size(imgs, n) bytes; needs no
  *                 initialisation (each call clears what it uses). Calls
  *                 sharing a workspace must not overlap.
+ * Ordering: compressions on one device never overlap. A call issued to
+ * another stream than the previous call waits (on the device) for the
+ * previous call to finish, so several streams may compress safely; the
+ * first such change of stream in a process waits on the host instead
+ * (hipDeviceSynchronize), after which every call records an event. A
+ * call into a stream that is being captured into a graph is not ordered
+ * this way; such a graph must not be replayed while another compression
+ * runs on the device (its bounded waits could then give up).
  * n <= 64. Errors: CMP_EINVAL, CMP_ENOSPC, CMP_EUNSUPPORTED, CMP_EHIP.
  */
 size_t     cmp_rle_workspace_size(const cmp_image* imgs, int32_t n);
@@ -304,6 +312,18 @@ cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_format fmt, ui
 cmp_status cmp_rle_decompress(const uint8_t* const* in, const uint64_t* in_bytes, int32_t n,
                               const cmp_image* out, int32_t* roi_out_dev, int32_t* status_dev,
                               void* stream);
+
+/*
+ * Occupancy of the RLE kernels, for frames composited asynchronously
+ * (Section 5.4: the stages of consecutive frames overlap). Both kernels run
+ * a resident grid that by default fills every compute unit; a cap of c
+ * workgroups per compute unit (1..) leaves room for the kernels of other
+ * streams, which pays when several frames are in flight and costs a
+ * single frame some speed. 0 restores the default. Process-wide, for all
+ * devices; affects calls issued afterwards. Results do not depend on it.
+ * Errors: CMP_EINVAL (a negative cap).
+ */
+cmp_status cmp_rle_set_groups_per_cu(int32_t compress, int32_t decompress);
 
 /*
  * Batched compositing: many independent jobs in one persistent launch whose

@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
         "cmp_rle_workspace_size": ([IMG, i32], sz),
         "cmp_rle_compress": ([IMG, i32, i32, ctypes.c_uint32, P, P, P, P, P, P, sz, P], i32),
         "cmp_rle_decompress": ([P, P, i32, IMG, P, P, P], i32),
+        "cmp_rle_set_groups_per_cu": ([i32, i32], i32),
         "cmp_batch_plan_create": ([ctypes.POINTER(CJob), i32, ctypes.c_char_p,
                                    ctypes.POINTER(P)], i32),
         "cmp_batch_workspace_size": ([P], sz),
@@ -394,6 +395,12 @@ def rle_compress(images: Sequence, roi_dev=None, swizzle=False, stream=None):
     """Per-component RLE of n images (cmp_rle_compress). Returns (streams,
     sizes): full-capacity uint8 buffers and an int64 tensor of stream sizes."""
     return RleBatch(images, roi_dev, swizzle=swizzle).run(stream)
+
+
+def rle_set_groups_per_cu(compress: int, decompress: int) -> None:
+    """Cap the RLE kernels' workgroups per compute unit (cmp_rle_set_groups_per_cu);
+    0 = as many as fit."""
+    _check(lib().cmp_rle_set_groups_per_cu(compress, decompress), "cmp_rle_set_groups_per_cu")
 
 
 def rle_decompress(streams: Sequence[torch.Tensor], outs: Sequence, stream=None, roi_out=None,

@@ -19,8 +19,10 @@
 //     one wave reading 64 predecessors' flags at a time.
 // The grid is at most one resident wave of workgroups, each taking the slots
 // (image, block) w, w + G, ... in a fixed order, so no ticket counter is
-// needed: the smallest unfinished slot always belongs to a running
-// workgroup. A small kernel clears the look-back flags before each call.
+// needed: the smallest unfinished slot always belongs to a workgroup that is
+// running, or that starts once other kernels' workgroups leave (the host
+// side keeps two compressions from sharing a device). A small kernel clears
+// the look-back flags before each call.
 // Every workgroup derives the slot count from the device ROIs, so blocks that
 // the ROIs leave out cost nothing.
 //
@@ -34,6 +36,8 @@
 // a row covers one 256-pixel segment, which no run crosses. Pixels are
 // assembled in registers and written with 16-byte stores.
 #include <string.h>
+
+#include <mutex>
 
 #include "cmp_internal.hpp"
 
@@ -993,20 +997,47 @@ __global__ __launch_bounds__(kThreads, 4) void rle_decompress_kernel(const RleDA
   }
 }
 
-// Workgroups of `kernel` that fit on the device at once (cached per device).
-static int resident_groups(const void* kernel, int* cache) {
+// Workgroups of `kernel` that fit on the device at once, at most `cap` per
+// compute unit when cap > 0 (the per-unit occupancy is cached per device).
+static int resident_groups(const void* kernel, int* cache, int cap) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
-  if (cache[dev] > 0) return cache[dev];
-  int cus = 0, per_cu = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess ||
-      cus <= 0 || per_cu <= 0)
-    return 1024;
-  cache[dev] = cus * per_cu;
-  return cache[dev];
+  if (cache[dev] <= 0) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess ||
+        cus <= 0 || per_cu <= 0)
+      return 1024;
+    cache[dev] = cus * 256 + per_cu;   // both fit: cus < 2^23, per_cu < 256
+  }
+  const int cus = cache[dev] / 256, per_cu = cache[dev] % 256;
+  return cus * (cap > 0 && cap < per_cu ? cap : per_cu);
 }
 static int g_compress_groups[64], g_decompress_groups[64];
+// Caps on the workgroups per compute unit (0: as many as fit).
+static int g_compress_cap = 0, g_decompress_cap = 0;
+
+// Compressions on one device never run at the same time. A compressing
+// workgroup may wait for a block of a workgroup that is not yet running;
+// alone on the device that workgroup starts as soon as any other kernel's
+// workgroups leave, but two compressions whose grids fill the device could
+// each hold the room the other one waits for. So every compression waits
+// (on the device, through an event) for the previous one when that one was
+// issued to another stream. Recording an event costs a few microseconds
+// in its stream, so it is recorded after a compression only once calls have
+// come from more than one stream; the first change of stream waits on the
+// host for the device instead (once). Launches into a stream being captured
+// into a graph are left out: a captured compression must not be replayed
+// while another compression runs.
+struct CompressOrder {
+  hipEvent_t ev = nullptr;
+  hipStream_t last = nullptr;
+  bool any = false;     // a compression was issued on this device
+  bool multi = false;   // calls have come from more than one stream: ev
+                        // follows the last compression
+};
+static std::mutex g_compress_mu;
+static CompressOrder g_compress_order[64];
 
 // Look-back flags: one per block of each image's largest possible ROI.
 static int64_t rle_flag_count(const cmp_image* imgs, int32_t n) {
@@ -1094,17 +1125,47 @@ extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_for
   a.n = n;
   a.swizzle = (flags & CMP_RLE_SWIZZLE) ? 1 : 0;
   hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  CMP_CHECK_HIP(hipGetDevice(&dev));
+  CMP_REQUIRE(dev >= 0 && dev < 64, "device %d: at most 64 devices", dev);
+  hipStreamCaptureStatus cap_st = hipStreamCaptureStatusNone;
+  CMP_CHECK_HIP(hipStreamIsCapturing(s, &cap_st));
+  const bool ordered = cap_st == hipStreamCaptureStatusNone;
+  std::lock_guard<std::mutex> lock(g_compress_mu);
+  CompressOrder& ord = g_compress_order[dev];
+  if (ordered) {
+    if (!ord.ev) CMP_CHECK_HIP(hipEventCreateWithFlags(&ord.ev, hipEventDisableTiming));
+    if (ord.any && ord.last != s) {
+      if (ord.multi)
+        CMP_CHECK_HIP(hipStreamWaitEvent(s, ord.ev, 0));
+      else
+        CMP_CHECK_HIP(hipDeviceSynchronize());   // the first change of stream
+      ord.multi = true;
+    }
+  }
   // clear the look-back flags (a kernel, so that graph replays clear them too)
   const int64_t cgrid = (nflags + kThreads - 1) / kThreads;
   hipLaunchKernelGGL(rle_clear_kernel, dim3((unsigned)(cgrid < 1024 ? cgrid : 1024)), dim3(kThreads),
                      0, s, a.flags, nflags);
   CMP_CHECK_HIP(hipGetLastError());
   // at most one resident wave of workgroups: every block a workgroup waits
-  // for belongs to a running workgroup
-  const int64_t cap = resident_groups((const void*)rle_compress_kernel, g_compress_groups);
+  // for belongs to a workgroup that is running or will start
+  const int64_t cap = resident_groups((const void*)rle_compress_kernel, g_compress_groups, g_compress_cap);
   hipLaunchKernelGGL(rle_compress_kernel, dim3((unsigned)(grid < cap ? grid : cap)), dim3(kThreads),
                      0, s, a);
   CMP_CHECK_HIP(hipGetLastError());
+  if (ordered) {
+    if (ord.multi) CMP_CHECK_HIP(hipEventRecord(ord.ev, s));
+    ord.last = s;
+    ord.any = true;
+  }
+  return CMP_OK;
+}
+
+extern "C" cmp_status cmp_rle_set_groups_per_cu(int32_t compress, int32_t decompress) {
+  CMP_REQUIRE(compress >= 0 && decompress >= 0, "caps must be >= 0 (0: as many as fit)");
+  g_compress_cap = compress;
+  g_decompress_cap = decompress;
   return CMP_OK;
 }
 
@@ -1137,7 +1198,7 @@ extern "C" cmp_status cmp_rle_decompress(const uint8_t* const* in, const uint64_
   a.roi_out = roi_out_dev;
   a.status = status_dev;
   a.n = n;
-  const int64_t cap = resident_groups((const void*)rle_decompress_kernel, g_decompress_groups);
+  const int64_t cap = resident_groups((const void*)rle_decompress_kernel, g_decompress_groups, g_decompress_cap);
   hipLaunchKernelGGL(rle_decompress_kernel, dim3((unsigned)(grid < cap ? grid : cap)),
                      dim3(kThreads), 0, (hipStream_t)stream, a);
   CMP_CHECK_HIP(hipGetLastError());

@@ -582,12 +582,16 @@ def test_ramp_pipeline_full_size():
     assert (ref_c == full_c).all() and (ref_d == full_d).all()
 
 
-def test_two_frames_in_flight_match_one_at_a_time():
-    """The benchmark's asynchronous mode: two frames' whole chains (ROI, RLE
-    compress, decompress, depth compositing) on two streams at once give the
-    same streams and composites as running them one after the other."""
-    note("two frames in flight")
-    frames = [synth.depth_ramps_full(seed=s, n=16, W=1920, H=1080, device=DEV) for s in (2, 3)]
+@pytest.mark.parametrize("nframes,groups_per_cu", [(2, 0), (4, 3)])
+def test_frames_in_flight_match_one_at_a_time(nframes, groups_per_cu):
+    """The benchmark's asynchronous mode: several frames' whole chains (ROI,
+    RLE compress, decompress, depth compositing) on as many streams at once,
+    with the RLE kernels' occupancy capped or not, give the same streams and
+    composites as running them one after the other (compressions on
+    different streams are ordered by the library)."""
+    note(f"{nframes} frames in flight, RLE groups per CU {groups_per_cu}")
+    frames = [synth.depth_ramps_full(seed=s, n=16, W=1920, H=1080, device=DEV)
+              for s in range(2, 2 + nframes)]
 
     def chain(wl, stream):
         with torch.cuda.stream(stream):
@@ -604,20 +608,25 @@ def test_two_frames_in_flight_match_one_at_a_time():
             placed = [cmp.Image(b.color, b.depth, (0, 0, 1920, 1080)) for b in blocks]
             oc, od = cmp.composite_depth(placed, wl.viewport, roi_dev=ro,
                                          schedule=("binary_swap", 16))
-        return roi, streams, sizes, st, oc, od
+        return roi, streams, sizes, st, oc, od, batch.status
 
     main = torch.cuda.current_stream()
     seq = [chain(wl, main) for wl in frames]
     torch.cuda.synchronize()
-    side = [torch.cuda.Stream(), torch.cuda.Stream()]
-    for st in side:
-        st.wait_stream(main)
-    par = [chain(wl, st) for wl, st in zip(frames, side)]
-    for st in side:
-        main.wait_stream(st)
-    torch.cuda.synchronize()
+    cmp.rle_set_groups_per_cu(groups_per_cu, groups_per_cu)
+    try:
+        side = [torch.cuda.Stream() for _ in frames]
+        for st in side:
+            st.wait_stream(main)
+        par = [chain(wl, st) for wl, st in zip(frames, side)]
+        for st in side:
+            main.wait_stream(st)
+        torch.cuda.synchronize()
+    finally:
+        cmp.rle_set_groups_per_cu(0, 0)
     for a, b in zip(seq, par):
         assert torch.equal(a[0], b[0])
+        assert (a[6] == 0).all() and (b[6] == 0).all()   # compression finished in time
         assert torch.equal(a[2], b[2]) and (a[3] == 0).all() and (b[3] == 0).all()
         for k in range(16):
             n = int(a[2][k])
