@@ -13,15 +13,17 @@ several copies of every buffer so that the 256 MB Infinity Cache cannot
 serve a step from the previous one.
 
 Prints one JSON line: Mpixel/s of composited input (the sum of the ROI areas
-supplied per frame) with frames composited asynchronously, two in flight on
-two streams (one frame at a time, as a HIP graph and eagerly, is reported
-beside it), the roofline of the dominant stage (algorithmic bytes over its
-event-timed average duration, one frame at a time), and the oracle timed on
-the host.
+supplied per frame) with frames composited asynchronously, three in flight
+on three streams with the RLE kernels at three workgroups per compute unit
+(one frame at a time, as a HIP graph and eagerly, at full occupancy, is
+reported beside it), the roofline of the dominant stage (algorithmic bytes
+over its event-timed average duration, one frame at a time), and the oracle
+timed on the host.
 """
 from __future__ import annotations
 
 import argparse
+import math
 import ctypes
 import json
 import os
@@ -148,16 +150,24 @@ def time_stages(frames, steps, warmup, s_obj):
     return total_ms, wall, per
 
 
+# Frames in flight in the headline run and the RLE kernels' workgroups per
+# compute unit there (measured over 1-6 frames and caps 3 / all: 3 and 3 are
+# fastest; a fourth frame adds contention rather than overlap)
+PIPE_IN_FLIGHT = 3
+PIPE_RLE_GROUPS = 3
+
+
 def time_pipelined(frames, steps, warmup, s_obj, in_flight=2):
     """Frames composited asynchronously (the thesis's pipelined compositing of
     consecutive frames, Section 5.4): step i runs the whole chain for buffer
-    copy i mod 4 on stream i mod in_flight, so `in_flight` frames overlap
+    copy i mod (copies) on stream i mod in_flight, so `in_flight` frames overlap
     (a ROI scan or a compositing pass of one frame next to the RLE kernels
     of another). Each copy's steps stay in order on their stream. Returns
     the milliseconds and wall seconds of `steps` steps between a
     synchronize on each side."""
-    streams = [torch.cuda.Stream() for _ in range(in_flight)]
     nf = len(frames)
+    assert nf % in_flight == 0, "each buffer copy must stay on one stream"
+    streams = [torch.cuda.Stream() for _ in range(in_flight)]
 
     def run(count):
         for i in range(count):
@@ -166,7 +176,9 @@ def time_pipelined(frames, steps, warmup, s_obj, in_flight=2):
             for k in range(4):
                 f.stage(k, st)
 
-    run(max(warmup, nf))
+    # the runtime's per-stream pools grow during the first few dozen steps
+    # with several streams busy: at least 64 untimed steps
+    run(max(warmup, nf, 64))
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -392,7 +404,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--copies", type=int, default=4, help="buffer copies rotated per step")
+    ap.add_argument("--copies", type=int, default=6,
+                    help="buffer copies rotated per step (a multiple of the frames in flight)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default="", help="profile helper: run only this stage (or probe_copy, a 1 GiB copy) "
@@ -435,6 +448,7 @@ def main():
     assert int(frames[0].status.abs().sum()) == 0 and int(frames[0].rle.status.abs().sum()) == 0
     sizes = frames[0].rle.sizes.cpu().numpy()
     abytes, roi_px = algorithmic_bytes(frames[0], rois, sizes)
+    ref_color = frames[0].out_c.clone()   # every copy holds the same workload
 
     if args.only:
         k = STAGES.index(args.only)
@@ -453,10 +467,24 @@ def main():
         stages[name] = {"us": float(stage_ms[k] * 1e3), "bytes": int(abytes[name]),
                         "GBps": float(abytes[name] / stage_ms[k] / 1e6)}
     dom = max(STAGES, key=lambda n: stages[n]["us"])
+    # several frames in flight: the RLE kernels leave a quarter of each
+    # compute unit to the other streams' kernels
+    in_flight = math.gcd(PIPE_IN_FLIGHT, len(frames))
+    cmp.rle_set_groups_per_cu(PIPE_RLE_GROUPS, PIPE_RLE_GROUPS)
+    try:
+        pipe_total, pipe_wall = time_pipelined(frames, args.steps, args.warmup, s_obj,
+                                               in_flight=in_flight)
+    finally:
+        cmp.rle_set_groups_per_cu(0, 0)
+    pipe_ms = pipe_total / args.steps
+    # one frame at a time as HIP graphs, after the asynchronous run: measured
+    # before it, graph capture left the first asynchronous run ~15% slower
     graph_total, graph_wall = time_graph(frames, args.steps, args.warmup, s_obj)
     graph_ms = graph_total / args.steps
-    pipe_total, pipe_wall = time_pipelined(frames, args.steps, args.warmup, s_obj)
-    pipe_ms = pipe_total / args.steps
+    # the timed runs left every copy's statuses clear and its composite intact
+    for f in frames:
+        assert int(f.status.abs().sum()) == 0 and int(f.rle.status.abs().sum()) == 0, "RLE status"
+        assert torch.equal(f.out_c, ref_color), "composite changed during the timed runs"
     probe = bandwidth_probe(dev)
     step_bytes = sum(abytes.values())
     achieved = stages[dom]["GBps"]
@@ -482,11 +510,13 @@ def main():
                    "contributors": 16, "width": 1920, "height": 1080,
                    "roi_area_fraction": "0.25-0.35", "schedule": "binary_swap(16)",
                    "composited_input_px_per_step": roi_px, "buffer_copies": args.copies},
-        "timing": "value and ms_per_step: frames composited asynchronously, 2 in flight (each "
-                  "frame's whole chain on one of 2 streams); graph: one frame at a time, its five "
+        "timing": f"value and ms_per_step: frames composited asynchronously, {in_flight} in "
+                  f"flight (each frame's whole chain on one of {in_flight} streams, RLE kernels "
+                  f"at {PIPE_RLE_GROUPS} workgroups per CU); graph: one frame at a time, its five "
                   "launches replayed as a HIP graph; stages and roofline: per-stage events of one "
-                  "frame at a time, eager",
-        "frames_in_flight": 2,
+                  "frame at a time, eager, RLE kernels at full occupancy",
+        "frames_in_flight": in_flight,
+        "pipelined_rle_groups_per_cu": PIPE_RLE_GROUPS,
         "graph_ms_per_step": graph_ms,
         "eager_ms_per_step": ms_step,
         "hbm_GBps_step": step_bytes / pipe_ms / 1e6,
