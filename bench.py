@@ -122,7 +122,37 @@ def algorithmic_bytes(frame, rois, stream_sizes):
     }, roi_px
 
 
+class DevEvent:
+    """A HIP timing event whose record releases to device scope only
+    (hipEventReleaseToDevice): torch's events release to system scope, which
+    writes back and invalidates the L2 at every record and would charge that
+    to the stage that follows."""
+    _hip = None
+
+    def __init__(self):
+        if DevEvent._hip is None:
+            DevEvent._hip = ctypes.CDLL("libamdhip64.so")
+        self.h = ctypes.c_void_p()
+        st = DevEvent._hip.hipEventCreateWithFlags(ctypes.byref(self.h), ctypes.c_uint(0x40000000))
+        assert st == 0, f"hipEventCreateWithFlags: {st}"
+
+    def record(self, stream_handle):
+        st = DevEvent._hip.hipEventRecord(self.h, ctypes.c_void_p(stream_handle))
+        assert st == 0, f"hipEventRecord: {st}"
+
+    def elapsed_ms(self, end):
+        ms = ctypes.c_float()
+        st = DevEvent._hip.hipEventElapsedTime(ctypes.byref(ms), self.h, end.h)
+        assert st == 0, f"hipEventElapsedTime: {st}"
+        return ms.value
+
+    def __del__(self):
+        if self.h and DevEvent._hip is not None:
+            DevEvent._hip.hipEventDestroy(self.h)
+
+
 def time_stages(frames, steps, warmup, s_obj):
+    """One frame at a time on one stream, each stage between two events."""
     s = s_obj.cuda_stream
     nf = len(frames)
     for i in range(warmup):
@@ -130,24 +160,42 @@ def time_stages(frames, steps, warmup, s_obj):
         for k in range(4):
             f.stage(k, s)
     torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
+    ev = [[DevEvent() for _ in range(5)] for _ in range(steps)]
+    t0, t1 = DevEvent(), DevEvent()
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    t0.record(s_obj)
+    t0.record(s)
     for i in range(steps):
         f = frames[i % nf]
         for k in range(4):
-            ev[i][k].record(s_obj)
+            ev[i][k].record(s)
             f.stage(k, s)
-        ev[i][4].record(s_obj)
-    t1.record(s_obj)
+        ev[i][4].record(s)
+    t1.record(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    total_ms = t0.elapsed_time(t1)
-    per = np.array([[ev[i][k].elapsed_time(ev[i][k + 1]) for k in range(4)] for i in range(steps)])
+    total_ms = t0.elapsed_ms(t1)
+    per = np.array([[ev[i][k].elapsed_ms(ev[i][k + 1]) for k in range(4)] for i in range(steps)])
     return total_ms, wall, per
+
+
+def time_stage_alone(frames, k, steps, warmup, s_obj):
+    """Stage k launched `steps` times back to back over the buffer copies
+    (its inputs are valid from the set-up pass), between two events: the
+    average milliseconds per launch, i.e. the stage's kernel time without
+    the gaps that per-stage events in the chain add."""
+    s = s_obj.cuda_stream
+    nf = len(frames)
+    for i in range(warmup):
+        frames[i % nf].stage(k, s)
+    t0, t1 = DevEvent(), DevEvent()
+    torch.cuda.synchronize()
+    t0.record(s)
+    for i in range(steps):
+        frames[i % nf].stage(k, s)
+    t1.record(s)
+    torch.cuda.synchronize()
+    return t0.elapsed_ms(t1) / steps
 
 
 # Frames in flight in the headline run and the RLE kernels' workgroups per
@@ -462,10 +510,12 @@ def main():
     total_ms, wall, per = time_stages(frames, args.steps, args.warmup, s_obj)
     ms_step = total_ms / args.steps
     stage_ms = per.mean(axis=0)
+    alone_ms = [time_stage_alone(frames, k, args.steps, args.warmup, s_obj) for k in range(4)]
     stages = {}
     for k, name in enumerate(STAGES):
-        stages[name] = {"us": float(stage_ms[k] * 1e3), "bytes": int(abytes[name]),
-                        "GBps": float(abytes[name] / stage_ms[k] / 1e6)}
+        stages[name] = {"us": float(alone_ms[k] * 1e3), "bytes": int(abytes[name]),
+                        "GBps": float(abytes[name] / alone_ms[k] / 1e6),
+                        "us_in_chain": float(stage_ms[k] * 1e3)}
     dom = max(STAGES, key=lambda n: stages[n]["us"])
     # several frames in flight: the RLE kernels leave a quarter of each
     # compute unit to the other streams' kernels
@@ -513,8 +563,10 @@ def main():
         "timing": f"value and ms_per_step: frames composited asynchronously, {in_flight} in "
                   f"flight (each frame's whole chain on one of {in_flight} streams, RLE kernels "
                   f"at {PIPE_RLE_GROUPS} workgroups per CU); graph: one frame at a time, its five "
-                  "launches replayed as a HIP graph; stages and roofline: per-stage events of one "
-                  "frame at a time, eager, RLE kernels at full occupancy",
+                  "launches replayed as a HIP graph; eager: the chain one frame at a time; stages "
+                  "and roofline: each stage launched back to back over the buffer copies between two "
+                  "events (us_in_chain: between per-stage events inside the eager chain), RLE "
+                  "kernels at full occupancy",
         "frames_in_flight": in_flight,
         "pipelined_rle_groups_per_cu": PIPE_RLE_GROUPS,
         "graph_ms_per_step": graph_ms,
