@@ -28,6 +28,15 @@ def test_exports_every_declared_function():
     assert not missing, missing
 
 
+def test_rle_occupancy_cap_arguments():
+    # host-side only: negative caps are rejected, 0 restores the default
+    L = cmp.lib()
+    assert L.cmp_rle_set_groups_per_cu(-1, 0) == cmp.CMP_EINVAL
+    assert L.cmp_rle_set_groups_per_cu(0, -2) == cmp.CMP_EINVAL
+    assert L.cmp_rle_set_groups_per_cu(3, 3) == cmp.CMP_OK
+    assert L.cmp_rle_set_groups_per_cu(0, 0) == cmp.CMP_OK
+
+
 def test_version_and_status_strings():
     assert "gfx950" in cmp.version()
     for s in (0, -1, -2, -3, -4, -5, -6):
