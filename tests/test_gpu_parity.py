@@ -177,6 +177,27 @@ def test_roi_detect_random_formats(fmt):
     assert [tuple(r) for r in roi.cpu().tolist()] == refs
 
 
+def test_roi_detect_tall_images_many_bands():
+    """Images tall enough that their bands hit the per-image limit of 1024
+    workgroups (the last workgroup folds 1024 partial boxes): data only in
+    the first and last bands, only in the last band, and none."""
+    h, w = 1_100_000, 32
+    a = np.full((h, w), F, np.uint32)
+    a[5, 31] = 7
+    a[h - 1, 0] = 9
+    a[h // 2, 10] = 1
+    b = np.full((h, w), F, np.uint32)
+    b[h - 3, 17] = 0
+    c = np.full((h, w), F, np.uint32)
+    imgs = [cmp.Image(*(2 * [torch.from_numpy(x.view(np.int32)).to(DEV)]), (0, 0, w, h))
+            for x in (a, b, c)]
+    note("roi tall images")
+    roi = cmp.roi_detect(imgs)
+    torch.cuda.synchronize()
+    assert [tuple(r) for r in roi.cpu().tolist()] == [oracle.roi_detect_depth(x) for x in (a, b, c)]
+    assert [tuple(r) for r in roi.cpu().tolist()] == [(0, 5, 32, h - 5), (17, h - 3, 1, 1), (0, 0, 0, 0)]
+
+
 # -------------------------------------------------------------------- RLE
 def _check_streams(imgs, rois, streams, sizes):
     for k, im in enumerate(imgs):
