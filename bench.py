@@ -335,10 +335,13 @@ def bench_over(dev, dtype, reps=10):
     del ow, out
     torch.cuda.empty_cache()
     return {"ms": ms, "Mpx_per_s": 64 * 3840 * 2160 / ms / 1e3, "GBps": nbytes / ms / 1e6,
-            "hbm_frac": nbytes / ms / 1e6 / PEAK_HBM_GBPS}
+            "hbm_frac": nbytes / ms / 1e6 / PEAK_HBM_GBPS, "bytes": nbytes}
 
 
-def bench_backward(dev, reps=10):
+EXTRAS_ONLY = ("over_fp32", "over_fp16", "over_backward", "batch")
+
+
+def bench_backward(dev, reps=10, which=("forward", "backward", "forward_backward")):
     ow = synth.over_bricks(seed=4, n=32, W=1024, H=1024, device=dev, with_target=True)
     imgs = ow.layers
     out = torch.empty((1024, 1024, 4), dtype=torch.float32, device=dev)
@@ -356,6 +359,8 @@ def bench_backward(dev, reps=10):
     for name, fn, nbytes in [("forward", fwd, px * (32 * 16 + 16)),
                              ("backward", bwd, px * (32 * 16 + 16 + 32 * 16)),
                              ("forward_backward", lambda: (fwd(), bwd()), px * (2 * 32 * 16 + 32 + 32 * 16))]:
+        if name not in which:
+            continue
         for _ in range(2):
             fn()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -367,11 +372,11 @@ def bench_backward(dev, reps=10):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         res[name] = {"ms": ms, "Mpx_per_s": 32 * px / ms / 1e3, "GBps": nbytes / ms / 1e6,
-                     "hbm_frac": nbytes / ms / 1e6 / PEAK_HBM_GBPS}
+                     "hbm_frac": nbytes / ms / 1e6 / PEAK_HBM_GBPS, "bytes": nbytes}
     return res
 
 
-def bench_batch(dev, reps=5, tune_path=None):
+def bench_batch(dev, reps=5, tune_path=None, which=("persistent_graph", "persistent", "plain_launches")):
     jobs = synth.batch_jobs(seed=5, njobs=256, device=dev)
     outs, keep = [], []
     arr = (cmp.CJob * len(jobs))()
@@ -419,12 +424,15 @@ def bench_batch(dev, reps=5, tune_path=None):
     items, wgs = ctypes.c_int64(), ctypes.c_int32()
     L.cmp_batch_info(plan, ctypes.byref(items), ctypes.byref(wgs))
     g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        L.cmp_batch_run(plan, ws.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    if "persistent_graph" in which:
+        with torch.cuda.graph(g):
+            L.cmp_batch_run(plan, ws.data_ptr(), torch.cuda.current_stream().cuda_stream)
     res = {}
     for name, fn in [("persistent_graph", lambda: g.replay()),
                      ("persistent", lambda: L.cmp_batch_run(plan, ws.data_ptr(), s.cuda_stream)),
                      ("plain_launches", lambda: L.cmp_batch_run_plain(plan, s.cuda_stream))]:
+        if name not in which:
+            continue
         for _ in range(2):
             fn()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -436,7 +444,7 @@ def bench_batch(dev, reps=5, tune_path=None):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         res[name] = {"ms": ms, "Mpx_per_s": in_px / ms / 1e3, "GBps": nbytes / ms / 1e6,
-                     "hbm_frac": nbytes / ms / 1e6 / PEAK_HBM_GBPS}
+                     "hbm_frac": nbytes / ms / 1e6 / PEAK_HBM_GBPS, "bytes": nbytes}
     res["jobs"] = len(jobs)
     res["work_items"] = int(items.value)
     res["workgroups"] = int(wgs.value)
@@ -456,8 +464,8 @@ def main():
                     help="buffer copies rotated per step (a multiple of the frames in flight)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", default="", help="profile helper: run only this stage (or probe_copy, a 1 GiB copy) "
-                    "repeatedly")
+    ap.add_argument("--only", default="", help="profile helper: run only this stage (or probe_copy, a 1 GiB copy; "
+                    "or an extra: over_fp32, over_fp16, over_backward, batch) repeatedly")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
@@ -465,6 +473,20 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.only in EXTRAS_ONLY:
+        # profile helper for the extras: `steps` timed launches after two warm-up ones
+        if args.only == "over_fp32":
+            r = bench_over(dev, torch.float32, reps=args.steps)
+        elif args.only == "over_fp16":
+            r = bench_over(dev, torch.float16, reps=args.steps)
+        elif args.only == "over_backward":
+            r = bench_backward(dev, reps=args.steps, which=("backward",))["backward"]
+        else:
+            r = bench_batch(dev, reps=args.steps, which=("persistent",), tune_path=os.path.join(
+                os.environ.get("TMPDIR", "/tmp"), "cmp_tune_cache.txt"))["persistent"]
+        log(f"ran {args.only} {args.steps} times: {r['ms']:.3f} ms, {r['bytes']} algorithmic bytes per launch")
+        print(json.dumps({"only": args.only, **r}))
+        return
     if args.only == "probe_copy":
         # reference kernel for scaling HBM counters: a 1 GiB copy (1 GiB read + 1 GiB written)
         nbytes = 1 << 30
