@@ -212,9 +212,10 @@ cmp_status cmp_assemble_pixels(const cmp_image* in, int32_t n, const int32_t* of
  *   CMP_RGBA32F / CMP_RGBA16F: any channel != 0.0 (-0.0 is empty, NaN is data).
  *   roi_out_dev  device int32[n][4]: image-local (x, y, w, h); an image
  *                without data gives (0, 0, 0, 0).
- *   workspace    device, >= cmp_roi_workspace_size(imgs, n) bytes, zero-filled
- *                before its first use (per-image tickets, then a partial box
-                per workgroup); every call leaves the tickets zeroed again.
+ *   workspace    device, >= cmp_roi_workspace_size(imgs, n) bytes (per-image
+ *                tickets, then a partial box per workgroup), zero-filled
+ *                before its first use; every call leaves the tickets zeroed
+ *                again.
  * Calls that share a workspace must not overlap. n <= 64.
  * Errors: CMP_EINVAL, CMP_ENOSPC (workspace), CMP_EHIP.
  */
