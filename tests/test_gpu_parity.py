@@ -277,6 +277,55 @@ def test_rle_adversarial_images():
             assert torch.equal(o.depth[:h, :w], im.depth[y:y + h, x:x + w])
 
 
+def test_roi_rle_sixty_four_images():
+    """The per-call maximum of 64 images: ROI detection on the device, then
+    compression with those ROIs and decompression, against the oracle; sizes
+    from 1x1 to 90x70, some images empty, colour-only and depth images."""
+    rng = np.random.default_rng(64)
+    imgs, refs = [], []
+    for k in range(64):
+        H, W = int(rng.integers(1, 71)), int(rng.integers(1, 91))
+        d = np.full((H, W), F, np.uint32)
+        c = np.zeros((H, W), np.uint32)
+        if k % 9 != 4:   # every ninth image holds no data
+            y0, x0 = int(rng.integers(0, H)), int(rng.integers(0, W))
+            y1, x1 = int(rng.integers(y0, H)) + 1, int(rng.integers(x0, W)) + 1
+            d[y0:y1, x0:x1] = rng.integers(0, 4, (y1 - y0, x1 - x0)) + 1000 * k
+            c[y0:y1, x0:x1] = rng.integers(0, 3, (y1 - y0, x1 - x0)).astype(np.uint32) * 0x01020304 + 1
+        has_depth = k % 5 != 1
+        tc = torch.from_numpy(c.view(np.int32)).to(DEV)
+        td = torch.from_numpy(d.view(np.int32)).to(DEV)
+        imgs.append(cmp.Image(tc, td if has_depth else None, (0, 0, W, H)))
+        refs.append(oracle.roi_detect_depth(d) if has_depth else oracle.roi_detect_rgba8(c))
+    note("roi + rle, 64 images")
+    # ROI per image kind (the depth test for images with depth, the colour test otherwise)
+    with_d = [k for k in range(64) if imgs[k].depth is not None]
+    without = [k for k in range(64) if imgs[k].depth is None]
+    roi = torch.zeros((64, 4), dtype=torch.int32, device=DEV)
+    roi[with_d] = cmp.roi_detect([imgs[k] for k in with_d])
+    roi[without] = cmp.roi_detect([imgs[k] for k in without])
+    torch.cuda.synchronize()
+    got = [tuple(r) for r in roi.cpu().tolist()]
+    assert got == refs
+    batch = cmp.RleBatch(imgs, roi_dev=roi)
+    streams, sizes = batch.run()
+    torch.cuda.synchronize()
+    assert int(batch.status.abs().sum()) == 0
+    _check_streams(imgs, got, streams, sizes)
+    outs = [cmp.Image(torch.zeros_like(im.color), None if im.depth is None else torch.zeros_like(im.depth),
+                      im.roi) for im in imgs]
+    ro, st = cmp.rle_decompress(streams, outs)
+    torch.cuda.synchronize()
+    assert (st == 0).all()
+    assert [tuple(r) for r in ro.cpu().tolist()] == got
+    for im, o, (x, y, w, h) in zip(imgs, outs, got):
+        if w * h == 0:
+            continue
+        assert torch.equal(o.color[:h, :w], im.color[y:y + h, x:x + w])
+        if im.depth is not None:
+            assert torch.equal(o.depth[:h, :w], im.depth[y:y + h, x:x + w])
+
+
 def test_rle_decompress_rejects_corrupt_streams():
     depth = np.array([[5, 5, F], [5, 3, F], [F, F, F], [F, F, 7]], np.uint32)
     color = np.where(depth != F, 0xFF332211, 0).astype(np.uint32)
