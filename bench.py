@@ -380,6 +380,14 @@ def bench_backward(dev, reps=10, which=("forward", "backward", "forward_backward
     return res
 
 
+def _union_area(rois, W, H):
+    """Pixels of the W x H viewport covered by at least one placement."""
+    cover = np.zeros((H, W), bool)
+    for x, y, w, h in rois:
+        cover[max(0, y):max(0, min(H, y + h)), max(0, x):max(0, min(W, x + w))] = True
+    return int(cover.sum())
+
+
 def bench_batch(dev, reps=5, tune_path=None, which=("persistent_graph", "persistent", "plain_launches")):
     jobs = synth.batch_jobs(seed=5, njobs=256, device=dev)
     outs, keep = [], []
@@ -397,7 +405,7 @@ def bench_batch(dev, reps=5, tune_path=None, which=("persistent_graph", "persist
             outs.append((oc, od))
             keep.append(imgs)
             cover = sum(r[2] * r[3] for r in (i.roi for i in wl.images))
-            covered = min(w * h, cover)
+            covered = _union_area([i.roi for i in wl.images], w, h)
             nbytes += 4 * cover + 4 * covered + 8 * w * h
             in_px += cover
         else:

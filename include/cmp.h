@@ -164,13 +164,23 @@ cmp_status cmp_composite_over(const cmp_image* in, int32_t n, cmp_format fmt,
  *                  gradient has in[i].roi.w x in[i].roi.h pixels with pitch
  *                  grad_pitch_layers[i] (host int64[n]) and is fully written
  *                  (zero where the layer does not reach the viewport).
- * n <= 64. Errors: CMP_EINVAL, CMP_EUNSUPPORTED, CMP_EHIP.
+ *   workspace      device, 16-byte aligned, >= cmp_over_backward_workspace_size(n)
+ *                  bytes (0, and NULL allowed, for n <= 64): the layer
+ *                  descriptors of a pass with more layers. Calls sharing a
+ *                  workspace must not overlap.
+ * The layers are visited in chunks of 32 positions: with more than 32, the
+ * alpha of the layers in front of the back chunk is read once more (a first
+ * pass that keeps the transmittance at every chunk's front edge).
+ * n <= 256. Errors: CMP_EINVAL, CMP_ENOSPC (workspace), CMP_EUNSUPPORTED
+ * (n > 256), CMP_EHIP.
  */
+size_t     cmp_over_backward_workspace_size(int32_t n);
 cmp_status cmp_composite_over_backward(const cmp_image* in, int32_t n, cmp_format fmt,
                                        const int32_t* order_b2f, cmp_rect viewport,
                                        const float* grad_out, int64_t grad_pitch,
                                        float* const* grad_layers,
-                                       const int64_t* grad_pitch_layers, void* stream);
+                                       const int64_t* grad_pitch_layers, void* workspace,
+                                       size_t ws_bytes, void* stream);
 
 /*
  * Subpixel compositing (Section 4.2.3, Subpixel: the default compositing
@@ -275,19 +285,21 @@ size_t cmp_rle_max_size(int32_t w, int32_t h, int32_t nplanes);
  *   capacity      host uint64[n]; must be >= cmp_rle_max_size(image w, h,
  *                 nplanes), which bounds every ROI's stream.
  *   out_size_dev  device uint64[n]: the stream sizes.
- *   status_dev    NULL or device int32[n]; a bounded wait that gives up
- *                 stores CMP_ETIMEOUT there (never expected).
+ *   status_dev    device int32[n] (required), zero before the call; receives
+ *                 CMP_ETIMEOUT if a block's bounded wait for its predecessors
+ *                 gave up (not expected: see below). Such a stream is
+ *                 unusable: the block's offset entry is set to 0xFFFFFFFF
+ *                 (decompression rejects it with CMP_ECORRUPT), its payload is
+ *                 not written, and out_size may be 0.
  *   workspace     device, >= cmp_rle_workspace_size(imgs, n) bytes; needs no
  *                 initialisation (each call clears what it uses). Calls
  *                 sharing a workspace must not overlap.
- * Ordering: compressions on one device never overlap. A call issued to
- * another stream than the previous call waits (on the device) for the
- * previous call to finish, so several streams may compress safely; the
- * first such change of stream in a process waits on the host instead
- * (hipDeviceSynchronize), after which every call records an event. A
- * call into a stream that is being captured into a graph is not ordered
- * this way; such a graph must not be replayed while another compression
- * runs on the device (its bounded waits could then give up).
+ * A block's payload offset is the sum of the sizes of the blocks before it
+ * in its image, found on the device while the blocks are encoded (one
+ * pass). Workgroups draw blocks from a ticket counter per image, in order,
+ * so a block only waits for blocks held by running workgroups: any number of
+ * compressions may run at once, on any streams, eagerly or replayed from
+ * HIP graphs, each with its own workspace.
  * n <= 64. Errors: CMP_EINVAL, CMP_ENOSPC, CMP_EUNSUPPORTED, CMP_EHIP.
  */
 size_t     cmp_rle_workspace_size(const cmp_image* imgs, int32_t n);
@@ -325,6 +337,15 @@ cmp_status cmp_rle_decompress(const uint8_t* const* in, const uint64_t* in_bytes
  * Errors: CMP_EINVAL (a negative cap).
  */
 cmp_status cmp_rle_set_groups_per_cu(int32_t compress, int32_t decompress);
+
+/*
+ * Test hook for the failure path of compression: the number of polls a
+ * block makes for its predecessors' sizes before it gives up (negative:
+ * the default of about a million). With a small limit, blocks whose
+ * predecessors are not yet done give up and report CMP_ETIMEOUT instead of
+ * waiting. Process-wide; affects calls issued afterwards.
+ */
+cmp_status cmp_rle_set_wait_limit(int32_t polls);
 
 /*
  * Batched compositing: many independent jobs in one persistent launch whose

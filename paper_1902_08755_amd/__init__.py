@@ -86,7 +86,8 @@ def lib() -> ctypes.CDLL:
         "cmp_composite_average": ([IMG, i32, Rect, P, i64, Schedule, Tile, P], i32),
         "cmp_assemble_pixels": ([IMG, i32, P, i32, i32, Rect, P, i64, P], i32),
         "cmp_composite_over": ([IMG, i32, i32, P, Rect, P, i64, Schedule, Tile, P], i32),
-        "cmp_composite_over_backward": ([IMG, i32, i32, P, Rect, P, i64, P, P, P], i32),
+        "cmp_composite_over_backward": ([IMG, i32, i32, P, Rect, P, i64, P, P, P, sz, P], i32),
+        "cmp_over_backward_workspace_size": ([i32], sz),
         "cmp_roi_workspace_size": ([IMG, i32], sz),
         "cmp_roi_detect": ([IMG, i32, i32, P, P, sz, P], i32),
         "cmp_roi_grid": ([IMG, i32, i32, i32, i32, P, P], i32),
@@ -95,6 +96,7 @@ def lib() -> ctypes.CDLL:
         "cmp_rle_compress": ([IMG, i32, i32, ctypes.c_uint32, P, P, P, P, P, P, sz, P], i32),
         "cmp_rle_decompress": ([P, P, i32, IMG, P, P, P], i32),
         "cmp_rle_set_groups_per_cu": ([i32, i32], i32),
+        "cmp_rle_set_wait_limit": ([i32], i32),
         "cmp_batch_plan_create": ([ctypes.POINTER(CJob), i32, ctypes.c_char_p,
                                    ctypes.POINTER(P)], i32),
         "cmp_batch_workspace_size": ([P], sz),
@@ -237,9 +239,13 @@ def composite_over_backward(layers: Sequence, order, viewport, grad_out, grads=N
     pitches = (ctypes.c_int64 * max(1, n))(*[_rgba_pitch(g) for g in grads])
     order_arr = (ctypes.c_int32 * max(1, n))(*[int(v) for v in order])
     grad_out = grad_out.contiguous()
+    need = lib().cmp_over_backward_workspace_size(n)
+    ws = workspace("over_backward", need) if need else None
     st = lib().cmp_composite_over_backward(_images(layers, "rgba"), n, fmt, order_arr,
                                            _rect(viewport), grad_out.data_ptr(),
-                                           _rgba_pitch(grad_out), ptrs, pitches, _stream(stream))
+                                           _rgba_pitch(grad_out), ptrs, pitches,
+                                           ws.data_ptr() if ws is not None else None,
+                                           ws.numel() if ws is not None else 0, _stream(stream))
     _check(st, "cmp_composite_over_backward")
     return grads
 
@@ -383,18 +389,27 @@ class RleBatch:
         self.ws = torch.zeros(max(need, 256), dtype=torch.uint8, device=dev)
 
     def run(self, stream=None):
+        self.status.zero_()
         st = lib().cmp_rle_compress(self.arr, self.n, RGBA8, self.flags, _cuda(self.roi_dev, "roi_dev"),
                                     self.out_ptrs, self.cap_arr, self.sizes.data_ptr(),
                                     self.status.data_ptr(), self.ws.data_ptr(), self.ws.numel(),
                                     _stream(stream))
         _check(st, "cmp_rle_compress")
-        return self.outs, self.sizes
+        return self.outs, self.sizes, self.status
 
 
 def rle_compress(images: Sequence, roi_dev=None, swizzle=False, stream=None):
     """Per-component RLE of n images (cmp_rle_compress). Returns (streams,
-    sizes): full-capacity uint8 buffers and an int64 tensor of stream sizes."""
+    sizes, status): full-capacity uint8 buffers, an int64 tensor of stream
+    sizes and an int32 tensor of per-image statuses (0, or CMP_ETIMEOUT for
+    a stream that must not be used)."""
     return RleBatch(images, roi_dev, swizzle=swizzle).run(stream)
+
+
+def rle_set_wait_limit(polls: int) -> None:
+    """Test hook (cmp_rle_set_wait_limit): polls before a compressing block
+    gives up waiting for its predecessors; negative restores the default."""
+    _check(lib().cmp_rle_set_wait_limit(int(polls)), "cmp_rle_set_wait_limit")
 
 
 def rle_set_groups_per_cu(compress: int, decompress: int) -> None:

@@ -182,8 +182,11 @@ static std::vector<TuneEntry> read_cache(const char* path) {
       continue;
     }
     TuneEntry e;
+    // a tile must be what the plain entry points accept (positive sides,
+    // area <= 65536); anything else is ignored and the default tile is used
     if (arch_ok && sscanf(line, "%d %d %d %d %d %d %lf", &e.key.kind, &e.key.fmt, &e.key.nb,
-                          &e.key.sb, &e.tile.w, &e.tile.h, &e.us) == 7)
+                          &e.key.sb, &e.tile.w, &e.tile.h, &e.us) == 7 &&
+        e.tile.w > 0 && e.tile.h > 0 && (int64_t)e.tile.w * e.tile.h <= 65536)
       v.push_back(e);
   }
   fclose(f);

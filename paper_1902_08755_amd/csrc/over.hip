@@ -62,14 +62,20 @@ __global__ __launch_bounds__(kThreads) void over_tree_kernel(const OverArgs a) {
 // For the pixel's covering layers in front-to-back order i, with
 // T_0 = 1, T_{i+1} = T_i (1 - a_i) and S_i = L_i + (1 - a_i) S_{i+1}:
 //     grad L_i = G T_i,   grad a_i += -T_i <G, S_{i+1}>.
-// The back-to-front sweep reads every layer once, builds S (FP64) and keeps
-// a_i and D_i = <G, S_{i+1}> per lane in LDS; the front-to-back sweep then
+// The positions (back to front) are taken in chunks of kChunk. Per chunk, a
+// back-to-front sweep reads every layer once, carries S (FP64) and keeps
+// a_i and D_i = <G, S_{i+1}> per lane in LDS; a front-to-back sweep then
 // forms T (FP64) from the kept a_i and writes the gradients. Nothing per
-// layer goes to memory. With more than kChunk layers, the back kChunk
-// positions are handled first, with T at their front edge computed by a
-// front-to-back pass over the alpha of the front chunk.
-constexpr int kBwdMax = 64;
+// layer goes to memory. The chunks run back to front, so S carries over;
+// the transmittance in front of each chunk (a checkpoint) comes from a first
+// pass over the alpha of the layers in front of the back chunk, front to
+// back, kept per lane in LDS (FP64). Only layers that reach the tile are
+// visited, kOverBatch of them per batch of unconditional loads (a lane the
+// layer does not cover reads the layer's first pixel and discards it).
 constexpr int kChunk = 32;
+constexpr int kBwdInline = 64;                        // descriptors in the kernel arguments
+constexpr int kBwdMaxLayers = 256;                    // with a descriptor workspace
+constexpr int kBwdCkpt = kBwdMaxLayers / kChunk - 1;  // checkpoints of the general kernel
 
 struct BwdDesc {
   const void* color;
@@ -80,7 +86,8 @@ struct BwdDesc {
 };
 
 struct BwdArgs {
-  BwdDesc c[kBwdMax];   // back to front
+  BwdDesc c[kBwdInline];   // back to front (n <= kBwdInline)
+  const BwdDesc* desc;     // device copy, back to front (n > kBwdInline)
   const float* gout;
   int64_t gout_pitch;
   int32_t vx, vy, vw, vh;
@@ -93,28 +100,84 @@ __device__ __forceinline__ bool covers(const BwdDesc& D, int X, int Y) {
   return X >= D.x && X < D.x + D.w && Y >= D.y && Y < D.y + D.h;
 }
 
-// One chunk: positions [j0, j1). S (in/out) is the composite of everything
-// behind the chunk; T is the transmittance in front of it.
+// Positions [j0, j1) (j1 - j0 <= 32) whose layers reach the tile, as a mask
+// (bit i: position j0 + i). Uniform.
+__device__ __forceinline__ uint32_t bwd_hits(const BwdDesc* __restrict__ d, int j0, int j1, int x0,
+                                             int y0, int tw, int th) {
+  uint32_t m = 0;
+  for (int j = j0; j < j1; ++j) {
+    const BwdDesc& D = d[j];
+    if (!tile_misses(uniform(D.x), uniform(D.y), uniform(D.w), uniform(D.h), x0, y0, tw, th))
+      m |= 1u << (j - j0);
+  }
+  return (uint32_t)uniform((int)m);
+}
+
 template <int FMT>
-__device__ __forceinline__ void bwd_chunk(const BwdDesc* __restrict__ d, int j0, int j1, int X,
-                                          int Y, const f32x4 G, double (&S)[4], double T,
+__device__ __forceinline__ float ld_alpha(const void* base, int64_t px) {
+  if constexpr (FMT == CMP_RGBA32F) {
+    return ((const __attribute__((address_space(1))) float*)base)[4 * px + 3];
+  } else {
+    return (float)((const __attribute__((address_space(1))) _Float16*)base)[4 * px + 3];
+  }
+}
+
+// T <- T * prod (1 - a_j) over the hit positions of [j0, j0 + 32), front to
+// back (descending positions).
+template <int FMT>
+__device__ __forceinline__ double bwd_alpha_product(const BwdDesc* __restrict__ d, int j0,
+                                                    uint32_t hits, int X, int Y, double T) {
+  while (hits) {   // uniform
+    float al[kOverBatch];
+    bool cov[kOverBatch];
+    const int first = 31 - __builtin_clz(hits);
+#pragma unroll
+    for (int k = 0; k < kOverBatch; ++k) {
+      const bool has = hits != 0;
+      const int i = has ? 31 - __builtin_clz(hits) : first;
+      hits &= ~(1u << i);
+      const BwdDesc& D = d[j0 + i];
+      const int dx = uniform(D.x), dy = uniform(D.y), dw = uniform(D.w), dh = uniform(D.h);
+      cov[k] = has && X >= dx && X < dx + dw && Y >= dy && Y < dy + dh;
+      al[k] = ld_alpha<FMT>(uniform_ptr(D.color),
+                            cov[k] ? (int64_t)(Y - dy) * uniform64(D.pitch) + (X - dx) : 0);
+    }
+#pragma unroll
+    for (int k = 0; k < kOverBatch; ++k)
+      if (cov[k]) T = T * (1.0 - (double)al[k]);
+  }
+  return T;
+}
+
+// One chunk: positions j0 + i for the set bits i of `hits`. S (in/out) is the
+// composite of everything behind the chunk; T is the transmittance in front
+// of it.
+template <int FMT>
+__device__ __forceinline__ void bwd_chunk(const BwdDesc* __restrict__ d, int j0, uint32_t hits,
+                                          int X, int Y, const f32x4 G, double (&S)[4], double T,
                                           float2 (*st)[kThreads]) {
   const double g0 = G.x, g1 = G.y, g2 = G.z, g3 = G.w;
   const int tid = threadIdx.x;
-  for (int jb = j0; jb < j1; jb += kOverBatch) {
+  uint32_t m = hits;
+  while (m) {   // uniform: back to front over the hit positions
     f32x4 L[kOverBatch];
-    bool cov[kOverBatch];
+    bool cov[kOverBatch], has[kOverBatch];
+    int pos[kOverBatch];
+    const int first = (int)__builtin_ctz(m);
 #pragma unroll
     for (int k = 0; k < kOverBatch; ++k) {
-      const int j = jb + k;
-      L[k] = f32x4{0.f, 0.f, 0.f, 0.f};
-      cov[k] = j < j1 && covers(d[j], X, Y);
-      if (cov[k]) L[k] = ld_rgba<FMT>(d[j].color, (int64_t)(Y - d[j].y) * d[j].pitch + (X - d[j].x));
+      has[k] = m != 0;
+      pos[k] = has[k] ? (int)__builtin_ctz(m) : first;
+      m &= m - 1u;
+      const BwdDesc& D = d[j0 + pos[k]];
+      const int dx = uniform(D.x), dy = uniform(D.y), dw = uniform(D.w), dh = uniform(D.h);
+      cov[k] = has[k] && X >= dx && X < dx + dw && Y >= dy && Y < dy + dh;
+      L[k] = widen(ld_raw<FMT>(uniform_ptr(D.color),
+                               cov[k] ? (int64_t)(Y - dy) * uniform64(D.pitch) + (X - dx) : 0));
     }
 #pragma unroll
     for (int k = 0; k < kOverBatch; ++k) {
-      const int j = jb + k;
-      if (j >= j1) break;
+      if (!has[k]) break;   // uniform
       float2 e = make_float2(0.f, 0.f);   // (alpha, D); alpha 0 leaves T unchanged
       if (cov[k]) {
         e.y = (float)(g0 * S[0] + g1 * S[1] + g2 * S[2] + g3 * S[3]);
@@ -125,13 +188,16 @@ __device__ __forceinline__ void bwd_chunk(const BwdDesc* __restrict__ d, int j0,
         S[2] = (double)L[k].z + t * S[2];
         S[3] = (double)L[k].w + t * S[3];
       }
-      st[j - j0][tid] = e;
+      st[pos[k]][tid] = e;
     }
   }
-  for (int j = j1 - 1; j >= j0; --j) {
-    const BwdDesc& Dd = d[j];
+  m = hits;
+  while (m) {   // uniform: front to back
+    const int i = 31 - __builtin_clz(m);
+    m &= ~(1u << i);
+    const BwdDesc& Dd = d[j0 + i];
     if (!covers(Dd, X, Y)) continue;
-    const float2 e = st[j - j0][tid];
+    const float2 e = st[i][tid];
     f32x4 g;
     g.x = (float)(g0 * T);
     g.y = (float)(g1 * T);
@@ -144,34 +210,57 @@ __device__ __forceinline__ void bwd_chunk(const BwdDesc* __restrict__ d, int j0,
   }
 }
 
-template <int FMT>
+// kInline: n <= kBwdInline, descriptors in the arguments, at most two chunks
+// (the back chunk's checkpoint stays in a register); otherwise descriptors
+// from the workspace and up to kBwdCkpt checkpoints in LDS.
+template <int FMT, bool kInline>
 __global__ __launch_bounds__(kThreads) void over_bwd_kernel(const BwdArgs a) {
   __shared__ float2 st[kChunk][kThreads];
+  __shared__ double tck[kInline ? 1 : kBwdCkpt][kThreads];
+  const BwdDesc* d = kInline ? a.c : a.desc;
   const int ty = blockIdx.x / a.tiles_x, tx = blockIdx.x - ty * a.tiles_x;
   const int x0 = a.vx + tx * a.tile_w, y0 = a.vy + ty * a.tile_h;
   const int tw = min(a.tile_w, a.vx + a.vw - x0), th = min(a.tile_h, a.vy + a.vh - y0);
   const int np = tw * th;
+  const int n = a.n, nch = (n + kChunk - 1) / kChunk;
   for (int p = threadIdx.x; p < np; p += kThreads) {
     const int r = p / tw;
     const int c = p - r * tw;
     const int X = x0 + c, Y = y0 + r;
     const f32x4 G =
         reinterpret_cast<const f32x4*>(a.gout)[(int64_t)(Y - a.vy) * a.gout_pitch + (X - a.vx)];
-    double S[4] = {0.0, 0.0, 0.0, 0.0};
-    if (a.n <= kChunk) {
-      bwd_chunk<FMT>(a.c, 0, a.n, X, Y, G, S, 1.0, st);
-    } else {
-      // transmittance in front of the back chunk: front chunk, front to back
-      double T1 = 1.0;
-      for (int j = a.n - 1; j >= kChunk; --j) {
-        const BwdDesc& D = a.c[j];
-        if (covers(D, X, Y))
-          T1 = T1 * (1.0 - (double)ld_rgba<FMT>(D.color, (int64_t)(Y - D.y) * D.pitch + (X - D.x)).w);
+    // checkpoints: the transmittance in front of chunks nch-2 .. 0
+    double T1 = 1.0;
+    {
+      double T = 1.0;
+      for (int ch = nch - 1; ch >= 1; --ch) {
+        const int j0 = ch * kChunk, j1 = min(n, j0 + kChunk);
+        T = bwd_alpha_product<FMT>(d, j0, bwd_hits(d, j0, j1, x0, y0, tw, th), X, Y, T);
+        if (kInline) T1 = T;
+        else tck[ch - 1][threadIdx.x] = T;
       }
-      bwd_chunk<FMT>(a.c, 0, kChunk, X, Y, G, S, T1, st);
-      bwd_chunk<FMT>(a.c, kChunk, a.n, X, Y, G, S, 1.0, st);
+    }
+    double S[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int ch = 0; ch < nch; ++ch) {
+      const int j0 = ch * kChunk, j1 = min(n, j0 + kChunk);
+      const double T = ch == nch - 1 ? 1.0 : kInline ? T1 : tck[ch][threadIdx.x];
+      bwd_chunk<FMT>(d, j0, bwd_hits(d, j0, j1, x0, y0, tw, th), X, Y, G, S, T, st);
     }
   }
+}
+
+// Copies up to kBwdInline descriptors from the arguments to device memory
+// (the workspace of a backward pass with more layers): a kernel rather than
+// a host copy, so that a captured graph carries the descriptors with it.
+struct BwdDescCopy {
+  BwdDesc c[kBwdInline];
+  BwdDesc* dst;
+  int32_t n;
+};
+static_assert(sizeof(BwdDescCopy) <= 4096, "kernel arguments must fit in 4 KiB");
+
+__global__ __launch_bounds__(kThreads) void bwd_desc_kernel(const BwdDescCopy a) {
+  for (int i = threadIdx.x; i < a.n; i += kThreads) a.dst[i] = a.c[i];
 }
 
 __global__ __launch_bounds__(kThreads) void zero_rgba_kernel(float* p, int64_t pitch, int w,
@@ -296,17 +385,31 @@ extern "C" cmp_status cmp_composite_over(const cmp_image* in, int32_t n, cmp_for
   return CMP_OK;
 }
 
+extern "C" size_t cmp_over_backward_workspace_size(int32_t n) {
+  return n > kBwdInline && n <= kBwdMaxLayers ? (size_t)n * sizeof(BwdDesc) : 0;
+}
+
 extern "C" cmp_status cmp_composite_over_backward(const cmp_image* in, int32_t n, cmp_format fmt,
                                                   const int32_t* order_b2f, cmp_rect viewport,
                                                   const float* grad_out, int64_t grad_pitch,
                                                   float* const* grad_layers,
                                                   const int64_t* grad_pitch_layers,
+                                                  void* workspace, size_t ws_bytes,
                                                   void* stream) {
   cmp_status st = validate_over_inputs(in, n, fmt, order_b2f);
   if (st != CMP_OK) return st;
-  if (n > kBwdMax) {
-    set_error("the backward pass supports at most %d layers", kBwdMax);
+  if (n > kBwdMaxLayers) {
+    set_error("the backward pass supports at most %d layers", kBwdMaxLayers);
     return CMP_EUNSUPPORTED;
+  }
+  if (n > kBwdInline) {
+    CMP_REQUIRE(workspace && ((uintptr_t)workspace & 15) == 0,
+                "n = %d > %d layers needs a 16-byte aligned workspace", n, kBwdInline);
+    if (ws_bytes < cmp_over_backward_workspace_size(n)) {
+      set_error("workspace of %zu bytes is smaller than %zu", ws_bytes,
+                cmp_over_backward_workspace_size(n));
+      return CMP_ENOSPC;
+    }
   }
   CMP_REQUIRE(rect_valid(viewport), "viewport has a negative size");
   CMP_REQUIRE(n == 0 || (grad_layers && grad_pitch_layers), "grad_layers is NULL");
@@ -339,11 +442,27 @@ extern "C" cmp_status cmp_composite_over_backward(const cmp_image* in, int32_t n
 
   BwdArgs a;
   memset(&a, 0, sizeof a);
-  for (int j = 0; j < n; ++j) {
+  auto desc = [&](int j) {
     const int li = order_b2f[j];
     const cmp_image& I = in[li];
-    a.c[j] = BwdDesc{I.color, grad_layers[li], I.pitch, grad_pitch_layers[li], I.roi.x, I.roi.y,
-                     rect_empty(I.roi) ? 0 : I.roi.w, rect_empty(I.roi) ? 0 : I.roi.h};
+    return BwdDesc{I.color, grad_layers[li], I.pitch, grad_pitch_layers[li], I.roi.x, I.roi.y,
+                   rect_empty(I.roi) ? 0 : I.roi.w, rect_empty(I.roi) ? 0 : I.roi.h};
+  };
+  if (n <= kBwdInline) {
+    for (int j = 0; j < n; ++j) a.c[j] = desc(j);
+  } else {
+    // the descriptors go to the workspace, kBwdInline per copy kernel
+    BwdDesc* dst = (BwdDesc*)workspace;
+    for (int j0 = 0; j0 < n; j0 += kBwdInline) {
+      BwdDescCopy cp;
+      memset(&cp, 0, sizeof cp);
+      cp.n = n - j0 < kBwdInline ? n - j0 : kBwdInline;
+      for (int j = 0; j < cp.n; ++j) cp.c[j] = desc(j0 + j);
+      cp.dst = dst + j0;
+      hipLaunchKernelGGL(bwd_desc_kernel, dim3(1), dim3(kThreads), 0, s, cp);
+      CMP_CHECK_HIP(hipGetLastError());
+    }
+    a.desc = dst;
   }
   a.gout = grad_out;
   a.gout_pitch = grad_pitch;
@@ -357,10 +476,18 @@ extern "C" cmp_status cmp_composite_over_backward(const cmp_image* in, int32_t n
   a.tiles_x = (viewport.w + a.tile_w - 1) / a.tile_w;
   const int64_t tiles = (int64_t)a.tiles_x * ((viewport.h + a.tile_h - 1) / a.tile_h);
   CMP_REQUIRE(tiles < (1ll << 24), "too many tiles");
-  if (fmt == CMP_RGBA32F)
-    hipLaunchKernelGGL(over_bwd_kernel<CMP_RGBA32F>, dim3((unsigned)tiles), dim3(kThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL(over_bwd_kernel<CMP_RGBA16F>, dim3((unsigned)tiles), dim3(kThreads), 0, s, a);
+  const dim3 grid((unsigned)tiles), block(kThreads);
+  if (n <= kBwdInline) {
+    if (fmt == CMP_RGBA32F)
+      hipLaunchKernelGGL((over_bwd_kernel<CMP_RGBA32F, true>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((over_bwd_kernel<CMP_RGBA16F, true>), grid, block, 0, s, a);
+  } else {
+    if (fmt == CMP_RGBA32F)
+      hipLaunchKernelGGL((over_bwd_kernel<CMP_RGBA32F, false>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((over_bwd_kernel<CMP_RGBA16F, false>), grid, block, 0, s, a);
+  }
   CMP_CHECK_HIP(hipGetLastError());
   return CMP_OK;
 }

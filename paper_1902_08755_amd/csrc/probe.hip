@@ -15,12 +15,17 @@ __global__ __launch_bounds__(kThreads) void probe_read_kernel(const u32x4* __res
   const int64_t stride = (int64_t)gridDim.x * kThreads;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n16;
        i += stride * kProbeUnroll) {
+    // unconditional loads (an index past the end reads the last unit and is
+    // discarded): a branch between loads would issue them one at a time
     u32x4 v[kProbeUnroll];
 #pragma unroll
-    for (int k = 0; k < kProbeUnroll; ++k)
-      v[k] = i + k * stride < n16 ? src[i + k * stride] : u32x4{0, 0, 0, 0};
+    for (int k = 0; k < kProbeUnroll; ++k) {
+      const int64_t j = i + k * stride;
+      v[k] = src[j < n16 ? j : n16 - 1];
+    }
 #pragma unroll
-    for (int k = 0; k < kProbeUnroll; ++k) acc ^= v[k].x ^ v[k].y ^ v[k].z ^ v[k].w;
+    for (int k = 0; k < kProbeUnroll; ++k)
+      if (i + k * stride < n16) acc ^= v[k].x ^ v[k].y ^ v[k].z ^ v[k].w;
   }
   if (acc == 0x9E3779B9u) sink[0] = acc;   // (practically) never taken; keeps the loads
 }
@@ -32,8 +37,10 @@ __global__ __launch_bounds__(kThreads) void probe_copy_kernel(const u32x4* __res
        i += stride * kProbeUnroll) {
     u32x4 v[kProbeUnroll];
 #pragma unroll
-    for (int k = 0; k < kProbeUnroll; ++k)
-      if (i + k * stride < n16) v[k] = src[i + k * stride];
+    for (int k = 0; k < kProbeUnroll; ++k) {
+      const int64_t j = i + k * stride;
+      v[k] = src[j < n16 ? j : n16 - 1];
+    }
 #pragma unroll
     for (int k = 0; k < kProbeUnroll; ++k)
       if (i + k * stride < n16) dst[i + k * stride] = v[k];

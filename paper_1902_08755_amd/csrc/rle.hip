@@ -37,7 +37,7 @@
 // assembled in registers and written with 16-byte stores.
 #include <string.h>
 
-#include <mutex>
+#include <atomic>
 
 #include "cmp_internal.hpp"
 
@@ -169,15 +169,24 @@ struct RleCArgs {
   const int32_t* roi_dev;
   uint64_t* out_size;
   int32_t* status;
+  uint32_t* tickets;       // workspace: a ticket counter per image, kTicketStride words apart
   uint64_t* flags;         // workspace: one flag per (image, block)
   int32_t n;
   int32_t swizzle;         // CMP_RLE_SWIZZLE
+  uint32_t wait_limit;     // look-back polls before a block gives up
 };
 static_assert(sizeof(RleCArgs) <= 4096, "kernel arguments must fit in 4 KiB");
 
+// Workspace: the ticket counters (one per image, each on its own 128-byte
+// line), then the look-back flags; rle_clear_kernel zeroes both before
+// every compression.
+constexpr int kTicketStride = 32;
+constexpr size_t kTicketBytes = (size_t)kRleMax * kTicketStride * 4;
+
 // look-back flag: status (2 bits) << 32 | value (32 bits); 0 = not ready.
-// The flags are cleared by rle_clear_kernel before every compression.
-constexpr uint64_t kAgg = 1, kIncl = 2;
+// kPoison marks a block whose offset is unknown (a bounded wait gave up):
+// neither it nor any later block of the image writes its payload.
+constexpr uint64_t kAgg = 1, kIncl = 2, kPoison = 3;
 constexpr int kLookback = 4;   // flags per lane per look-back step
 __device__ __forceinline__ uint64_t mkflag(uint64_t st, uint32_t v) { return (st << 32) | v; }
 
@@ -266,19 +275,57 @@ struct CSlot {
   int s, b, rx, ry, rw, rh;
 };
 
-__device__ __forceinline__ CSlot compress_slot(uint32_t g, int n, const int4* t_roi,
-                                               const uint32_t* t_slots, const uint32_t* t_incl,
-                                               int lane) {
+__device__ __forceinline__ CSlot compress_slot(int2 sb, const int4* t_roi) {
   CSlot c;
-  const uint64_t hit = __ballot(lane < n && g < t_incl[lane]);
-  c.s = uniform(__builtin_ctzll(hit));
-  c.b = uniform((int)(g - (t_incl[c.s] - t_slots[c.s])));
+  c.s = uniform(sb.x);
+  c.b = uniform(sb.y);
   const int4 r = t_roi[c.s];
   c.rx = uniform(r.x);
   c.ry = uniform(r.y);
   c.rw = uniform(r.z);
   c.rh = uniform(r.w);
   return c;
+}
+
+// Draws the next slot for the calling workgroup (one wave calls it; the
+// result is uniform): ticket t of image s is block t of s. The blocks of an
+// image are handed out in order, and only to running workgroups, so every
+// block a look-back waits for belongs to a workgroup that runs; no launch
+// order, grid size or other kernel on the device can stall it. A workgroup
+// keeps drawing from its current image `img`; when that one is exhausted,
+// the wave reads every image's counter at once and moves to the image with
+// the most blocks left. Returns (-1, 0) when every image is exhausted.
+// The first ticket is drawn by draw_ticket (lane 0 of the wave), so that its
+// latency can pass while the wave works; draw_slot completes the draw.
+__device__ __forceinline__ uint32_t draw_ticket(uint32_t* tickets, int img) {
+  uint32_t t = 0;
+  if (threadIdx.x % kWave == 0)
+    t = __hip_atomic_fetch_add(&tickets[img * kTicketStride], 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+  return t;
+}
+
+__device__ __forceinline__ int2 draw_slot(uint32_t t0, uint32_t* tickets, const uint32_t* t_slots,
+                                          int n, int& img) {
+  const int lane = threadIdx.x % kWave;
+  uint32_t t = t0;
+  while (true) {
+    t = (uint32_t)__builtin_amdgcn_readlane((int)t, 0);
+    if (t < t_slots[img]) return int2{img, (int)t};
+    // exhausted: the image with the most blocks left (lane i reads image i)
+    uint32_t left = 0;
+    if (lane < n) {
+      const uint32_t c = __hip_atomic_load(&tickets[lane * kTicketStride], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+      left = c < t_slots[lane] ? t_slots[lane] - c : 0u;
+    }
+    uint32_t best = left;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) best = max(best, (uint32_t)__shfl_xor((int)best, m));
+    if (best == 0) return int2{-1, 0};
+    img = uniform((int)__builtin_ctzll(__ballot(left == best)));
+    t = draw_ticket(tickets, img);
+  }
 }
 
 // Issues the loads of this lane's 16 pixels of slot c (zeros past the block).
@@ -351,12 +398,14 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
   __shared__ __attribute__((aligned(16))) uint8_t stage[kStage];
   __shared__ uint32_t sh[16];
   __shared__ uint32_t s_excl;
+  __shared__ int32_t s_poison;
 
   // Slots: one per block of every image's ROI (an empty ROI still takes one
   // slot, whose workgroup writes the header-only stream). Wave 0 computes the
-  // table (lane i: image i, n <= 64; one load, then a wave scan) into LDS.
+  // table (lane i: image i, n <= 64; one load) into LDS.
   __shared__ int4 t_roi[kRleMax];
-  __shared__ uint32_t t_slots[kRleMax], t_incl[kRleMax], t_total;
+  __shared__ uint32_t t_slots[kRleMax];
+  __shared__ int2 s_next;   // the slot drawn for the next iteration
   {
     const int tid = threadIdx.x, lane = tid % kWave;
     if (tid < kWave) {
@@ -377,34 +426,31 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
         const uint32_t nb = (uint32_t)rle_nblocks((int64_t)lw * lh);
         lslots = nb ? nb : 1;
       }
-      uint32_t lincl = lslots;
-#pragma unroll
-      for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t o = __shfl_up(lincl, d);
-        if (lane >= d) lincl += o;
-      }
       t_roi[lane] = int4{lx, ly, lw, lh};
       t_slots[lane] = lslots;
-      t_incl[lane] = lincl;
-      if (lane == kWave - 1) t_total = lincl;
     }
   }
   __syncthreads();
-  const uint32_t total = t_total;
 
-  // Slots are taken in a fixed order: workgroup w does slots w, w + G, ...
-  // A block waits only for smaller slots of its image; the smallest
-  // unfinished slot always belongs to a running workgroup that has finished
-  // its earlier slots, so the waits always end (and are bounded anyway).
-  // The pixels of a workgroup's next slot are loaded while it finishes the
-  // current one (look-back and writes).
-  uint32_t col[kPxPerLane], dep[kPxPerLane];
-  CSlot nx{0, 0, 0, 0, 0, 0};
-  if (blockIdx.x < total) {
-    nx = compress_slot(blockIdx.x, a.n, t_roi, t_slots, t_incl, threadIdx.x % kWave);
-    compress_load(a, nx, threadIdx.x, col, dep);
+  // Slots come from per-image tickets (draw_slot), drawn by wave 1 one
+  // slot ahead: the next slot is drawn while the current one is encoded, and
+  // its pixels are loaded while the current one finishes (look-back and
+  // writes). Holding a drawn slot while finishing the current one cannot
+  // deadlock: a block only waits for blocks whose tickets were drawn
+  // earlier, so every chain of waits ends at a workgroup that makes
+  // progress.
+  int img = (int)(blockIdx.x % (uint32_t)a.n);   // wave 1's current image
+  if (threadIdx.x / kWave == 1) {
+    const int2 sb = draw_slot(draw_ticket(a.tickets, img), a.tickets, t_slots, a.n, img);
+    if (threadIdx.x == kWave) s_next = sb;
   }
-  for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
+  __syncthreads();
+  int2 cur = s_next;
+  if (cur.x < 0) return;   // uniform: nothing left for this workgroup
+  uint32_t col[kPxPerLane], dep[kPxPerLane];
+  CSlot nx = compress_slot(cur, t_roi);
+  compress_load(a, nx, threadIdx.x, col, dep);
+  while (true) {
   // an opaque copy of the thread index: keeps per-lane values from being
   // hoisted out of the loop and held in registers across iterations
   int tid = threadIdx.x;
@@ -412,7 +458,17 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
   const int lane = tid % kWave;
   const CSlot c = nx;
   const int s = c.s, b = c.b, rx = c.rx, ry = c.ry, rw = c.rw, rh = c.rh;
-  const bool more = g + gridDim.x < total;
+  // the next slot: its ticket is drawn now, the draw is completed (and
+  // written to s_next) just before the next barrier
+  const bool drawer = tid / kWave == 1;
+  const uint32_t t_next = drawer ? draw_ticket(a.tickets, img) : 0u;
+  auto finish_draw = [&]() {
+    if (drawer) {
+      const int2 sb = draw_slot(t_next, a.tickets, t_slots, a.n, img);
+      if (lane == 0) s_next = sb;
+    }
+  };
+  bool more = false;
   {
     const RleCImg I = a.im[s];
     const int np = I.depth ? 8 : 4;
@@ -421,8 +477,12 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
     const uint64_t P0 = rle_p0(nb, np);
     uint8_t* out = I.out;
     if (nb == 0) {
+      finish_draw();
+      __syncthreads();   // s_next is written
+      cur = s_next;
+      more = cur.x >= 0;
       if (more) {
-        nx = compress_slot(g + gridDim.x, a.n, t_roi, t_slots, t_incl, lane);
+        nx = compress_slot(cur, t_roi);
         compress_load(a, nx, tid, col, dep);
       }
       if (tid < 8) {
@@ -475,7 +535,10 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
         cnt[k >> 1] |= (uint32_t)__builtin_popcount(m) << (16 * (k & 1));
       }
       uint32_t ex[4], tot[4];
-      block_scan32<4>(cnt, ex, tot, sh);
+      finish_draw();
+      block_scan32<4>(cnt, ex, tot, sh);   // its barriers also publish s_next
+      cur = s_next;
+      more = cur.x >= 0;
 
       // ---- plane sizes and offsets (uniform)
       uint32_t size[8], poff[8];
@@ -540,6 +603,7 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
       // inclusive prefix, and moves the window back if it has none
       if (tid < kWave) {
         uint32_t excl = 0;
+        bool poisoned = false;
         if (b != 0) {
           int top = b - 1;   // flag i of lane l: predecessor top - (64 i + l)
           uint32_t spins = 0;
@@ -551,28 +615,34 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
               f[i] = mkflag(kIncl, 0);   // before block 0: an empty prefix
               if (p >= 0) f[i] = __hip_atomic_load(&flags[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            // the nearest inclusive prefix (distance 64 i + lane), and whether
-            // every flag up to it is ready
+            // the nearest inclusive (or poisoned) prefix, at distance
+            // 64 i + lane, and whether every flag up to it is ready
             int first = kWave * kLookback;
             bool waiting = false;
 #pragma unroll
             for (int i = kLookback - 1; i >= 0; --i) {
               const uint64_t st = (f[i] >> 32) & 3u;
-              const uint64_t incl = __ballot(st == kIncl);
+              const uint64_t incl = __ballot(st >= kIncl);
               if (incl) first = kWave * i + (int)__builtin_ctzll(incl);
             }
+            uint64_t pz = 0;
 #pragma unroll
             for (int i = 0; i < kLookback; ++i) {
               const uint64_t st = (f[i] >> 32) & 3u;
               if (__ballot(st == 0 && kWave * i + lane <= first)) waiting = true;
+              pz |= __ballot(st == kPoison && kWave * i + lane == first);
             }
             if (waiting) {
-              if (++spins > (1u << 20)) {
-                if (lane == 0 && a.status) a.status[s] = CMP_ETIMEOUT;
+              if (++spins > a.wait_limit) {   // never expected: see draw_slot
+                poisoned = true;
                 break;
               }
               __builtin_amdgcn_s_sleep(1);
               continue;
+            }
+            if (pz) {   // the prefix this block needs is unknown
+              poisoned = true;
+              break;
             }
             uint32_t v = 0;
 #pragma unroll
@@ -585,19 +655,24 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
             top -= kWave * kLookback;
           }
           if (lane == 0)
-            __hip_atomic_store(&flags[b], mkflag(kIncl, excl + padded), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&flags[b], poisoned ? mkflag(kPoison, 0) : mkflag(kIncl, excl + padded),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (lane == 0) s_excl = excl;
+        if (lane == 0) {
+          s_excl = excl;
+          s_poison = poisoned ? 1 : 0;
+          if (poisoned) a.status[s] = CMP_ETIMEOUT;
+        }
       }
       // the next slot's pixels go in flight: waves 1..3 during the look-back,
       // wave 0 after it (its flag loads must not wait behind these loads)
       if (more) {
-        nx = compress_slot(g + gridDim.x, a.n, t_roi, t_slots, t_incl, lane);
+        nx = compress_slot(cur, t_roi);
         compress_load(a, nx, tid, col, dep);
       }
       __syncthreads();
       const uint32_t excl = s_excl;
+      const bool poisoned = s_poison != 0;
 
       // ---- tables, header, payload
       uint32_t* tbl = reinterpret_cast<uint32_t*>(out + 32);
@@ -608,7 +683,10 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
           if (k == tid) v = size[k];
         tbl[nb + (uint64_t)b * np + tid] = v;
       }
-      if (tid == 0) tbl[b] = excl;
+      // a poisoned block's offset is unknown: its table entry is made invalid
+      // (not a multiple of 16, which decompression rejects) and its payload
+      // is not written
+      if (tid == 0) tbl[b] = poisoned ? 0xFFFFFFFFu : excl;
       if (b == 0) {
         if (tid < 8) {
           const uint32_t hdr[8] = {kRleMagic, (uint32_t)rx, (uint32_t)ry, (uint32_t)rw,
@@ -619,13 +697,16 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
         const uint64_t tend = 32 + 4 * nb * (1 + (uint64_t)np);
         if ((uint64_t)tid < P0 - tend) out[tend + tid] = 0;
       }
-      if ((uint64_t)b == nb - 1 && tid == 0) a.out_size[s] = P0 + excl + padded;
-      u32x4* dst = reinterpret_cast<u32x4*>(out + P0 + excl);
-      const u32x4* src = reinterpret_cast<const u32x4*>(stage);
-      for (uint32_t i = tid; i < padded / 16; i += kThreads) dst[i] = src[i];
+      if ((uint64_t)b == nb - 1 && tid == 0) a.out_size[s] = poisoned ? 0 : P0 + excl + padded;
+      if (!poisoned) {
+        u32x4* dst = reinterpret_cast<u32x4*>(out + P0 + excl);
+        const u32x4* src = reinterpret_cast<const u32x4*>(stage);
+        for (uint32_t i = tid; i < padded / 16; i += kThreads) dst[i] = src[i];
+      }
     }
   }
-  __syncthreads();   // the stage and the scan words are reused by the next slot
+  __syncthreads();   // the stage, the scan words and s_next are reused by the next slot
+  if (!more) break;
   }
 }
 
@@ -999,45 +1080,28 @@ __global__ __launch_bounds__(kThreads, 4) void rle_decompress_kernel(const RleDA
 
 // Workgroups of `kernel` that fit on the device at once, at most `cap` per
 // compute unit when cap > 0 (the per-unit occupancy is cached per device).
-static int resident_groups(const void* kernel, int* cache, int cap) {
+static int resident_groups(const void* kernel, std::atomic<int>* cache, int cap) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
-  if (cache[dev] <= 0) {
+  int packed = cache[dev].load(std::memory_order_relaxed);
+  if (packed <= 0) {
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess ||
         cus <= 0 || per_cu <= 0)
       return 1024;
-    cache[dev] = cus * 256 + per_cu;   // both fit: cus < 2^23, per_cu < 256
+    packed = cus * 256 + per_cu;   // both fit: cus < 2^23, per_cu < 256
+    cache[dev].store(packed, std::memory_order_relaxed);
   }
-  const int cus = cache[dev] / 256, per_cu = cache[dev] % 256;
+  const int cus = packed / 256, per_cu = packed % 256;
   return cus * (cap > 0 && cap < per_cu ? cap : per_cu);
 }
-static int g_compress_groups[64], g_decompress_groups[64];
+static std::atomic<int> g_compress_groups[64], g_decompress_groups[64];
 // Caps on the workgroups per compute unit (0: as many as fit).
-static int g_compress_cap = 0, g_decompress_cap = 0;
-
-// Compressions on one device never run at the same time. A compressing
-// workgroup may wait for a block of a workgroup that is not yet running;
-// alone on the device that workgroup starts as soon as any other kernel's
-// workgroups leave, but two compressions whose grids fill the device could
-// each hold the room the other one waits for. So every compression waits
-// (on the device, through an event) for the previous one when that one was
-// issued to another stream. Recording an event costs a few microseconds
-// in its stream, so it is recorded after a compression only once calls have
-// come from more than one stream; the first change of stream waits on the
-// host for the device instead (once). Launches into a stream being captured
-// into a graph are left out: a captured compression must not be replayed
-// while another compression runs.
-struct CompressOrder {
-  hipEvent_t ev = nullptr;
-  hipStream_t last = nullptr;
-  bool any = false;     // a compression was issued on this device
-  bool multi = false;   // calls have come from more than one stream: ev
-                        // follows the last compression
-};
-static std::mutex g_compress_mu;
-static CompressOrder g_compress_order[64];
+static std::atomic<int> g_compress_cap{0}, g_decompress_cap{0};
+// Look-back polls before a compressing block gives up (negative: the default).
+constexpr uint32_t kDefaultWaitLimit = 1u << 20;
+static std::atomic<int32_t> g_wait_limit{-1};
 
 // Look-back flags: one per block of each image's largest possible ROI.
 static int64_t rle_flag_count(const cmp_image* imgs, int32_t n) {
@@ -1067,7 +1131,7 @@ extern "C" size_t cmp_rle_max_size(int32_t w, int32_t h, int32_t nplanes) {
 
 extern "C" size_t cmp_rle_workspace_size(const cmp_image* imgs, int32_t n) {
   if (n < 0 || (n > 0 && !imgs)) return 0;
-  return (size_t)(8 * rle_flag_count(imgs, n));
+  return kTicketBytes + (size_t)(8 * rle_flag_count(imgs, n));
 }
 
 extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_format fmt,
@@ -1081,11 +1145,12 @@ extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_for
     set_error("RLE compression handles RGBA8 (+ depth) pixels");
     return CMP_EUNSUPPORTED;
   }
-  CMP_REQUIRE(imgs && out && capacity && out_size_dev && workspace, "NULL argument");
+  CMP_REQUIRE(imgs && out && capacity && out_size_dev && status_dev && workspace, "NULL argument");
   CMP_REQUIRE((flags & ~CMP_RLE_SWIZZLE) == 0, "unknown flags 0x%x", flags);
   CMP_REQUIRE(((uintptr_t)roi_dev & 15) == 0 && ((uintptr_t)workspace & 15) == 0 &&
-                  ((uintptr_t)out_size_dev & 7) == 0,
-              "roi_dev/workspace must be 16-byte and out_size_dev 8-byte aligned");
+                  ((uintptr_t)out_size_dev & 7) == 0 && ((uintptr_t)status_dev & 3) == 0,
+              "roi_dev/workspace must be 16-byte, out_size_dev 8-byte and status_dev "
+              "4-byte aligned");
   RleCArgs a;
   memset(&a, 0, sizeof a);
   int64_t grid = 0, nflags = 0;
@@ -1113,7 +1178,7 @@ extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_for
     grid += nb ? nb : 1;
   }
   CMP_REQUIRE(grid < (1ll << 24), "too many blocks");
-  const size_t need = (size_t)(8 * nflags);
+  const size_t need = kTicketBytes + (size_t)(8 * nflags);
   if (ws_bytes < need) {
     set_error("workspace of %zu bytes is smaller than %zu", ws_bytes, need);
     return CMP_ENOSPC;
@@ -1121,51 +1186,38 @@ extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_for
   a.roi_dev = roi_dev;
   a.out_size = out_size_dev;
   a.status = status_dev;
-  a.flags = (uint64_t*)workspace;
+  a.tickets = (uint32_t*)workspace;
+  a.flags = (uint64_t*)((uint8_t*)workspace + kTicketBytes);
   a.n = n;
   a.swizzle = (flags & CMP_RLE_SWIZZLE) ? 1 : 0;
+  const int32_t wl = g_wait_limit.load(std::memory_order_relaxed);
+  a.wait_limit = wl < 0 ? kDefaultWaitLimit : (uint32_t)wl;
   hipStream_t s = (hipStream_t)stream;
-  int dev = 0;
-  CMP_CHECK_HIP(hipGetDevice(&dev));
-  CMP_REQUIRE(dev >= 0 && dev < 64, "device %d: at most 64 devices", dev);
-  hipStreamCaptureStatus cap_st = hipStreamCaptureStatusNone;
-  CMP_CHECK_HIP(hipStreamIsCapturing(s, &cap_st));
-  const bool ordered = cap_st == hipStreamCaptureStatusNone;
-  std::lock_guard<std::mutex> lock(g_compress_mu);
-  CompressOrder& ord = g_compress_order[dev];
-  if (ordered) {
-    if (!ord.ev) CMP_CHECK_HIP(hipEventCreateWithFlags(&ord.ev, hipEventDisableTiming));
-    if (ord.any && ord.last != s) {
-      if (ord.multi)
-        CMP_CHECK_HIP(hipStreamWaitEvent(s, ord.ev, 0));
-      else
-        CMP_CHECK_HIP(hipDeviceSynchronize());   // the first change of stream
-      ord.multi = true;
-    }
-  }
-  // clear the look-back flags (a kernel, so that graph replays clear them too)
-  const int64_t cgrid = (nflags + kThreads - 1) / kThreads;
+  // clear the tickets and the look-back flags (a kernel, so that graph
+  // replays clear them too)
+  const int64_t nclear = (int64_t)(kTicketBytes / 8) + nflags;
+  const int64_t cgrid = (nclear + kThreads - 1) / kThreads;
   hipLaunchKernelGGL(rle_clear_kernel, dim3((unsigned)(cgrid < 1024 ? cgrid : 1024)), dim3(kThreads),
-                     0, s, a.flags, nflags);
+                     0, s, (uint64_t*)workspace, nclear);
   CMP_CHECK_HIP(hipGetLastError());
-  // at most one resident wave of workgroups: every block a workgroup waits
-  // for belongs to a workgroup that is running or will start
-  const int64_t cap = resident_groups((const void*)rle_compress_kernel, g_compress_groups, g_compress_cap);
+  // one wave of workgroups at most: more would find the tickets drawn
+  const int64_t cap = resident_groups((const void*)rle_compress_kernel, g_compress_groups,
+                                      g_compress_cap.load(std::memory_order_relaxed));
   hipLaunchKernelGGL(rle_compress_kernel, dim3((unsigned)(grid < cap ? grid : cap)), dim3(kThreads),
                      0, s, a);
   CMP_CHECK_HIP(hipGetLastError());
-  if (ordered) {
-    if (ord.multi) CMP_CHECK_HIP(hipEventRecord(ord.ev, s));
-    ord.last = s;
-    ord.any = true;
-  }
+  return CMP_OK;
+}
+
+extern "C" cmp_status cmp_rle_set_wait_limit(int32_t polls) {
+  g_wait_limit.store(polls < 0 ? -1 : polls, std::memory_order_relaxed);
   return CMP_OK;
 }
 
 extern "C" cmp_status cmp_rle_set_groups_per_cu(int32_t compress, int32_t decompress) {
   CMP_REQUIRE(compress >= 0 && decompress >= 0, "caps must be >= 0 (0: as many as fit)");
-  g_compress_cap = compress;
-  g_decompress_cap = decompress;
+  g_compress_cap.store(compress, std::memory_order_relaxed);
+  g_decompress_cap.store(decompress, std::memory_order_relaxed);
   return CMP_OK;
 }
 
@@ -1198,7 +1250,8 @@ extern "C" cmp_status cmp_rle_decompress(const uint8_t* const* in, const uint64_
   a.roi_out = roi_out_dev;
   a.status = status_dev;
   a.n = n;
-  const int64_t cap = resident_groups((const void*)rle_decompress_kernel, g_decompress_groups, g_decompress_cap);
+  const int64_t cap = resident_groups((const void*)rle_decompress_kernel, g_decompress_groups,
+                                      g_decompress_cap.load(std::memory_order_relaxed));
   hipLaunchKernelGGL(rle_decompress_kernel, dim3((unsigned)(grid < cap ? grid : cap)),
                      dim3(kThreads), 0, (hipStream_t)stream, a);
   CMP_CHECK_HIP(hipGetLastError());

@@ -143,9 +143,23 @@ def test_over_argument_errors():
     gl = (ctypes.c_void_p * 3)(0x30000, 0x30000, 0x30000)
     gp = (ctypes.c_int64 * 3)(8, 8, 4)
     assert L.cmp_composite_over_backward(ok, 3, cmp.RGBA32F, order(0, 1, 2), vp, 0x40000, 8, gl,
-                                         gp, None) == cmp.CMP_EINVAL
+                                         gp, None, 0, None) == cmp.CMP_EINVAL
+    # more than 64 layers: the descriptors need a workspace; at most 256 layers
+    assert L.cmp_over_backward_workspace_size(64) == 0
+    need = L.cmp_over_backward_workspace_size(65)
+    assert need >= 65 * 40 and L.cmp_over_backward_workspace_size(257) == 0
+    gl65 = (ctypes.c_void_p * 65)(*([0x30000] * 65))
+    gp65 = (ctypes.c_int64 * 65)(*([8] * 65))
     assert L.cmp_composite_over_backward(big, 65, cmp.RGBA32F, order(*range(65)), vp, 0x40000, 8,
-                                         gl, gp, None) == cmp.CMP_EUNSUPPORTED
+                                         gl65, gp65, None, 0, None) == cmp.CMP_EINVAL
+    assert L.cmp_composite_over_backward(big, 65, cmp.RGBA32F, order(*range(65)), vp, 0x40000, 8,
+                                         gl65, gp65, 0x50000, need - 16, None) == cmp.CMP_ENOSPC
+    huge = _arr([_img((0, 0, 8, 8), color=0x10000, depth=None)] * 257)
+    gl257 = (ctypes.c_void_p * 257)(*([0x30000] * 257))
+    gp257 = (ctypes.c_int64 * 257)(*([8] * 257))
+    assert L.cmp_composite_over_backward(huge, 257, cmp.RGBA32F, order(*range(257)), vp, 0x40000,
+                                         8, gl257, gp257, 0x50000, 1 << 20,
+                                         None) == cmp.CMP_EUNSUPPORTED
 
 
 def test_roi_and_rle_argument_errors():
@@ -164,15 +178,19 @@ def test_roi_and_rle_argument_errors():
     need = cmp.rle_max_size(64, 64, 8)
     caps = (ctypes.c_uint64 * 2)(need, need - 1)
     wsz = L.cmp_rle_workspace_size(imgs, 2)
-    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA8, 0, None, outs, caps, 0x3000, None, 0x4000, wsz,
+    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA8, 0, None, outs, caps, 0x3000, 0x3800, 0x4000, wsz,
                               None) == cmp.CMP_ENOSPC
     caps[1] = need
-    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA8, 0, None, outs, caps, 0x3000, None, 0x4000, wsz - 8,
+    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA8, 0, None, outs, caps, 0x3000, 0x3800, 0x4000, wsz - 8,
                               None) == cmp.CMP_ENOSPC
-    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA32F, 0, None, outs, caps, 0x3000, None, 0x4000, wsz,
+    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA32F, 0, None, outs, caps, 0x3000, 0x3800, 0x4000, wsz,
                               None) == cmp.CMP_EUNSUPPORTED
+    # the status array is required
+    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA8, 0, None, outs, caps, 0x3000, None, 0x4000, wsz,
+                              None) == cmp.CMP_EINVAL
+    assert L.cmp_rle_set_wait_limit(5) == 0 and L.cmp_rle_set_wait_limit(-1) == 0
     bad = (ctypes.c_void_p * 2)(0x100008, 0x200000)
-    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA8, 0, None, bad, caps, 0x3000, None, 0x4000, wsz,
+    assert L.cmp_rle_compress(imgs, 2, cmp.RGBA8, 0, None, bad, caps, 0x3000, 0x3800, 0x4000, wsz,
                               None) == cmp.CMP_EINVAL
     ins = (ctypes.c_void_p * 1)(0x100004)
     nb = (ctypes.c_uint64 * 1)(100)

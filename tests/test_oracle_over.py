@@ -53,6 +53,33 @@ def test_worked_example_adjoint():
         assert grads[i][0, 0, 1] == 0 and grads[i][0, 0, 2] == 0
 
 
+def test_worked_example_adjoint_scale():
+    """The componentwise condition scale that every GPU backward tolerance is
+    multiplied by, pinned to hand-worked values: with G >= 0 (nothing
+    cancels), and with a mixed-sign G whose alpha terms partly cancel."""
+    g, names, layers = _golden_layers()
+    rois, vp = [(0, 0, 1, 1)] * 3, (0, 0, 1, 1)
+    G = np.zeros((1, 1, 4))
+    G[0, 0, 0] = 0.3125
+    _, scale = oracle.composite_over_backward(layers, rois, [0, 1, 2], vp, G, want_scale=True)
+    sc = {r[0]: float(r[1]) for r in g["gscale_c"]}
+    sa = {r[0]: float(r[1]) for r in g["gscale_alpha"]}
+    for i, nm in enumerate(names):
+        assert scale[i][0, 0, 0] == sc[nm]
+        assert scale[i][0, 0, 3] == sa[nm]
+        assert scale[i][0, 0, 1] == 0 and scale[i][0, 0, 2] == 0
+    G[0, 0, 3] = -0.5
+    grads, scale = oracle.composite_over_backward(layers, rois, [0, 1, 2], vp, G, want_scale=True)
+    gam = {r[0]: float(r[1]) for r in g["grad_alpha_mixed"]}
+    sam = {r[0]: float(r[1]) for r in g["gscale_alpha_mixed"]}
+    for i, nm in enumerate(names):
+        assert grads[i][0, 0, 0] == sc[nm]   # G_0 >= 0: |grad c| = its scale
+        assert grads[i][0, 0, 3] == gam[nm]
+        assert scale[i][0, 0, 3] == sam[nm]
+        # the scale bounds the gradient's own magnitude
+        assert abs(grads[i][0, 0, 3]) <= scale[i][0, 0, 3]
+
+
 def _rand_layers(rng, n, W, H, full=False, dtype=np.float64):
     layers, rois = [], []
     for _ in range(n):
