@@ -85,6 +85,12 @@ def lib():
         L.orc_rle_header.restype = ctypes.c_int
         L.orc_rle_decompress.argtypes = [P, u64, P, P, i64, ctypes.POINTER(Rect)]
         L.orc_rle_decompress.restype = ctypes.c_int
+        L.orc_rle64_max_size.argtypes = [i32, i32, i32]
+        L.orc_rle64_max_size.restype = u64
+        L.orc_rle64_compress.argtypes = [P, P, i64, Rect, P, u64]
+        L.orc_rle64_compress.restype = u64
+        L.orc_rle64_decompress.argtypes = [P, u64, P, P, i64, ctypes.POINTER(Rect)]
+        L.orc_rle64_decompress.restype = ctypes.c_int
         L.orc_composite_average_rgba8.argtypes = [i32, P, P, P, Rect, P, i64]
         L.orc_composite_average_rgba8.restype = None
         L.orc_assemble_pixels.argtypes = [i32, P, P, P, P, i32, i32, Rect, P, i64]
@@ -304,6 +310,48 @@ def rle_decompress(stream):
                                   max(w, 1), ctypes.byref(r))
     if rc != 0:
         raise CorruptStream("corrupt payload")
+    return r.tup(), c, d
+
+
+def rle64_max_size(w, h, nstreams):
+    return int(lib().orc_rle64_max_size(w, h, nstreams))
+
+
+def rle64_compress(color, depth, roi):
+    """Basic 64-bit RLE of the ROI of an RGBA8 (+ depth) image (Section
+    5.5.1: two pixels per 64-bit token). Returns the RL64 stream (uint8)."""
+    c = _contig(color, np.uint32)
+    d = None if depth is None else _contig(depth, np.uint32)
+    if d is not None:
+        assert d.shape == c.shape
+    x, y, w, h = roi
+    assert 0 <= x and 0 <= y and x + w <= c.shape[1] and y + h <= c.shape[0]
+    ns = 1 if d is None else 2
+    cap = rle64_max_size(w, h, ns)
+    out = np.zeros(cap, np.uint8)
+    sz = lib().orc_rle64_compress(_ptr(c), None if d is None else _ptr(d), c.shape[1],
+                                  Rect(*roi), _ptr(out), cap)
+    if sz == 0:
+        raise ValueError("rle64_compress failed")
+    return out[:sz].copy()
+
+
+def rle64_decompress(stream):
+    """Decode an RL64 stream. Returns (roi, color, depth or None)."""
+    s = np.ascontiguousarray(np.asarray(stream, dtype=np.uint8))
+    if s.size < 32:
+        raise CorruptStream("short header")
+    hw = s[:32].view(np.uint32)
+    w, h, ns = int(hw[3]), int(hw[4]), int(hw[5])
+    if w < 0 or h < 0 or w > (1 << 20) or h > (1 << 20):
+        raise CorruptStream("bad size")
+    c = np.zeros((h, w), np.uint32)
+    d = np.zeros((h, w), np.uint32) if ns == 2 else None
+    r = Rect()
+    rc = lib().orc_rle64_decompress(_ptr(s), s.size, _ptr(c), None if d is None else _ptr(d),
+                                    max(w, 1), ctypes.byref(r))
+    if rc != 0:
+        raise CorruptStream("corrupt stream")
     return r.tup(), c, d
 
 

@@ -584,6 +584,219 @@ int orc_rle_decompress(const uint8_t* in, uint64_t size, uint32_t* out_color, ui
 }
 
 /* ------------------------------------------------------------------------ */
+/* Basic 64-bit RLE (Section 5.5.1, Enhanced RLE Compression: the basic     */
+/* compressor compares two RGBA8 pixels at a time, as one 64-bit token, so  */
+/* it only compresses runs of equal pixel pairs). The thesis gives no       */
+/* stream format; the "RL64" format is defined here, with the block and     */
+/* table layout of RLE1.                                                    */
+/*                                                                          */
+/* Symbols: the ROI's colour words row-major, in pairs: symbol j holds      */
+/* pixel 2j in its low 32 bits and pixel 2j+1 in its high 32 bits (an odd   */
+/* last pixel of a block pairs with 0). With a depth buffer the depth words */
+/* form a second symbol stream the same way. Blocks of 4096 pixels, i.e.    */
+/* m = ceil(len / 2) symbols. Runs are maximal runs of equal symbols that   */
+/* do not cross a multiple of 128 symbols (256 pixels): 1..128 symbols. A   */
+/* stream of a block with R runs is stored as tokens when                   */
+/* align8(R) + 8 R < 8 m: the R bytes (run length - 1), zero bytes up to a  */
+/* multiple of 8, then the R run values as little-endian 64-bit words;      */
+/* otherwise as its m symbols (8 m bytes). size == 8 m marks raw.           */
+/* Layout: as RLE1 (header, boff[nblocks], size[nblocks][nstreams], zero    */
+/* bytes to a multiple of 16, payloads padded to 16) with magic 0x34364C52  */
+/* ("RL64") and header word 5 = nstreams (1: colour, 2: colour + depth).    */
+/* ------------------------------------------------------------------------ */
+#define RL64_MAGIC 0x34364C52u
+#define RL64_SEG 128   /* symbols per 256-pixel segment */
+
+static uint64_t align8(uint64_t v) { return (v + 7u) & ~(uint64_t)7u; }
+
+static void put64(uint8_t* p, uint64_t v)
+{
+    for (int i = 0; i < 8; ++i) p[i] = (uint8_t)(v >> (8 * i));
+}
+
+static uint64_t get64(const uint8_t* p)
+{
+    uint64_t v = 0;
+    for (int i = 0; i < 8; ++i) v |= (uint64_t)p[i] << (8 * i);
+    return v;
+}
+
+static int64_t blk_len(int64_t npx, uint64_t b)
+{
+    const int64_t rest = npx - (int64_t)b * RLE_BLOCK;
+    return rest < RLE_BLOCK ? rest : RLE_BLOCK;
+}
+
+uint64_t orc_rle64_max_size(int32_t w, int32_t h, int32_t nstreams)
+{
+    const int64_t npx = (int64_t)w * h;
+    const uint64_t nb = rle_nblocks(npx);
+    uint64_t total = rle_payload_start(nb, nstreams);
+    for (uint64_t b = 0; b < nb; ++b)
+        total += align16(8 * (uint64_t)nstreams * (uint64_t)((blk_len(npx, b) + 1) / 2));
+    return total;
+}
+
+/* symbol j of stream k (0 colour, 1 depth) of the block starting at pixel q0 */
+static uint64_t rl64_symbol(const uint32_t* color, const uint32_t* depth, int64_t pitch,
+                            orc_rect roi, int64_t q0, int64_t len, int k, int64_t j)
+{
+    const uint32_t* src = k == 0 ? color : depth;
+    uint64_t v = 0;
+    for (int half = 0; half < 2; ++half) {
+        const int64_t p = 2 * j + half;   /* block-relative pixel */
+        if (p >= len) break;              /* the odd last pixel pairs with 0 */
+        const int64_t q = q0 + p;
+        const int64_t yy = q / roi.w, xx = q % roi.w;
+        v |= (uint64_t)src[(roi.y + yy) * pitch + (roi.x + xx)] << (32 * half);
+    }
+    return v;
+}
+
+/* Returns the stream size, or 0 if `cap` is too small or the ROI invalid. */
+uint64_t orc_rle64_compress(const uint32_t* color, const uint32_t* depth, int64_t pitch,
+                            orc_rect roi, uint8_t* out, uint64_t cap)
+{
+    const int32_t ns = depth ? 2 : 1;
+    if (roi.w < 0 || roi.h < 0) return 0;
+    if (roi.w == 0 || roi.h == 0) { roi.x = 0; roi.y = 0; roi.w = 0; roi.h = 0; }
+    const int64_t npx = (int64_t)roi.w * roi.h;
+    const uint64_t nb = rle_nblocks(npx);
+    const uint64_t P0 = rle_payload_start(nb, ns);
+    if (cap < orc_rle64_max_size(roi.w, roi.h, ns)) return 0;
+    memset(out, 0, P0);
+    put32(out + 0, RL64_MAGIC);
+    put32(out + 4, (uint32_t)roi.x); put32(out + 8, (uint32_t)roi.y);
+    put32(out + 12, (uint32_t)roi.w); put32(out + 16, (uint32_t)roi.h);
+    put32(out + 20, (uint32_t)ns);
+    put32(out + 24, RLE_BLOCK); put32(out + 28, (uint32_t)nb);
+    uint8_t* boff = out + 32;
+    uint8_t* sizes = out + 32 + 4 * nb;
+    uint64_t pos = 0;
+    static uint64_t sym[RLE_BLOCK / 2];
+    for (uint64_t b = 0; b < nb; ++b) {
+        const int64_t q0 = (int64_t)b * RLE_BLOCK;
+        const int64_t len = blk_len(npx, b);
+        const int64_t m = (len + 1) / 2;
+        put32(boff + 4 * b, (uint32_t)pos);
+        uint64_t block_bytes = 0;
+        for (int k = 0; k < ns; ++k) {
+            for (int64_t j = 0; j < m; ++j) sym[j] = rl64_symbol(color, depth, pitch, roi, q0, len, k, j);
+            /* runs of equal symbols inside a 128-symbol segment */
+            int64_t R = 0;
+            for (int64_t j = 0; j < m;) {
+                int64_t e = j + 1;
+                while (e < m && sym[e] == sym[j] && e % RL64_SEG != 0) ++e;
+                ++R;
+                j = e;
+            }
+            uint8_t* dst = out + P0 + pos + block_bytes;
+            uint32_t sz;
+            if (align8((uint64_t)R) + 8 * (uint64_t)R < 8 * (uint64_t)m) {
+                const uint64_t vals = align8((uint64_t)R);
+                int64_t t = 0;
+                for (int64_t j = 0; j < m;) {
+                    int64_t e = j + 1;
+                    while (e < m && sym[e] == sym[j] && e % RL64_SEG != 0) ++e;
+                    dst[t] = (uint8_t)(e - j - 1);
+                    put64(dst + vals + 8 * t, sym[j]);
+                    ++t;
+                    j = e;
+                }
+                for (uint64_t p = (uint64_t)R; p < vals; ++p) dst[p] = 0;
+                sz = (uint32_t)(vals + 8 * (uint64_t)R);
+            } else {
+                for (int64_t j = 0; j < m; ++j) put64(dst + 8 * j, sym[j]);
+                sz = (uint32_t)(8 * m);
+            }
+            put32(sizes + 4 * (b * ns + k), sz);
+            block_bytes += sz;
+        }
+        const uint64_t padded = align16(block_bytes);
+        for (uint64_t p = block_bytes; p < padded; ++p) out[P0 + pos + p] = 0;
+        pos += padded;
+    }
+    return P0 + pos;
+}
+
+/* Decodes an RL64 stream into ROI-sized buffers (w x h, out_pitch);        */
+/* out_depth is needed for two-stream streams. Returns 0, or -1 if the      */
+/* stream is corrupt: a bad header, tables that disagree, runs that do not  */
+/* add up to the block's symbols or cross a multiple of 128 symbols, a      */
+/* token size that does not match its run count, nonzero padding bytes, or  */
+/* a nonzero partner of an odd last pixel.                                   */
+int orc_rle64_decompress(const uint8_t* in, uint64_t size, uint32_t* out_color,
+                         uint32_t* out_depth, int64_t out_pitch, orc_rect* roi_out)
+{
+    if (size < 32 || get32(in) != RL64_MAGIC) return -1;
+    orc_rect r;
+    r.x = (int32_t)get32(in + 4); r.y = (int32_t)get32(in + 8);
+    r.w = (int32_t)get32(in + 12); r.h = (int32_t)get32(in + 16);
+    const uint32_t ns = get32(in + 20);
+    if (r.w < 0 || r.h < 0 || (ns != 1 && ns != 2) || get32(in + 24) != RLE_BLOCK) return -1;
+    const int64_t npx = (int64_t)r.w * r.h;
+    const uint64_t nb = rle_nblocks(npx);
+    if (get32(in + 28) != nb) return -1;
+    const uint64_t P0 = rle_payload_start(nb, (int32_t)ns);
+    if (size < P0) return -1;
+    if (ns == 2 && !out_depth) return -1;
+    static uint64_t sym[RLE_BLOCK / 2];
+    uint64_t pos = 0;
+    for (uint64_t b = 0; b < nb; ++b) {
+        const int64_t q0 = (int64_t)b * RLE_BLOCK;
+        const int64_t len = blk_len(npx, b);
+        const int64_t m = (len + 1) / 2;
+        if (get32(in + 32 + 4 * b) != pos) return -1;
+        uint64_t block_bytes = 0;
+        for (uint32_t k = 0; k < ns; ++k) {
+            const uint64_t sz = get32(in + 32 + 4 * nb + 4 * (b * ns + k));
+            if (P0 + pos + block_bytes + sz > size) return -1;
+            const uint8_t* src = in + P0 + pos + block_bytes;
+            if (sz > 8 * (uint64_t)m) return -1;
+            if (sz == 8 * (uint64_t)m) {
+                for (int64_t j = 0; j < m; ++j) sym[j] = get64(src + 8 * j);
+            } else {
+                /* run lengths until the block's symbols are covered */
+                int64_t j = 0, t = 0;
+                while (j < m) {
+                    if ((uint64_t)t >= sz) return -1;
+                    const int64_t run = (int64_t)src[t] + 1;
+                    if (j + run > m || (j % RL64_SEG) + run > RL64_SEG) return -1;
+                    j += run;
+                    ++t;
+                }
+                const uint64_t vals = align8((uint64_t)t);
+                if (sz != vals + 8 * (uint64_t)t) return -1;
+                for (uint64_t p = (uint64_t)t; p < vals; ++p)
+                    if (src[p] != 0) return -1;
+                j = 0;
+                for (int64_t u = 0; u < t; ++u) {
+                    const int64_t run = (int64_t)src[u] + 1;
+                    const uint64_t v = get64(src + vals + 8 * u);
+                    for (int64_t e = 0; e < run; ++e) sym[j + e] = v;
+                    j += run;
+                }
+            }
+            if ((len & 1) && (sym[m - 1] >> 32) != 0) return -1;
+            uint32_t* dst = k == 0 ? out_color : out_depth;
+            for (int64_t p = 0; p < len; ++p) {
+                const int64_t q = q0 + p;
+                const int64_t yy = q / r.w, xx = q % r.w;
+                dst[yy * out_pitch + xx] = (uint32_t)(sym[p / 2] >> (32 * (p & 1)));
+            }
+            block_bytes += sz;
+        }
+        const uint64_t padded = align16(block_bytes);
+        if (P0 + pos + padded > size) return -1;
+        for (uint64_t p = block_bytes; p < padded; ++p)
+            if (in[P0 + pos + p] != 0) return -1;
+        pos += padded;
+    }
+    if (roi_out) *roi_out = r;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Subpixel compositing (Section 4.2.3, Subpixel: the default compositing   */
 /* accumulates and averages all the computed fragments of a pixel; it       */
 /* reuses the parallel compositing of sort-last rendering except for this   */
