@@ -310,6 +310,28 @@ cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_format fmt, ui
                             void* stream);
 
 /*
+ * cmp_rle_compress without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). The tickets and look-back flags live in
+ * a fixed array inside the library: CMP_RLE_SCRATCH_BYTES bytes on every
+ * device it runs on, held until the process ends, its address looked up on
+ * the first call on each device. The call allocates nothing.
+ * Every call on a device shares that array: calls that overlap on one device
+ * (on other streams, or graph replays running at the same time) race and
+ * corrupt each other's streams; order them. Each call clears what it uses.
+ * Limit: cmp_rle_workspace_size(imgs, n) <= CMP_RLE_SCRATCH_BYTES, i.e. at
+ * most 131072 blocks of 4096 pixels over the n images (64 images of
+ * 3840x2160 fit); beyond it CMP_ENOSPC and nothing is launched. Arguments,
+ * results and other errors as cmp_rle_compress; CMP_EHIP if the array's
+ * address cannot be found.
+ */
+#define CMP_RLE_SCRATCH_BYTES ((size_t)8192 + (size_t)8 * 131072)
+cmp_status cmp_rle_compress_noalloc(const cmp_image* imgs, int32_t n, cmp_format fmt,
+                                    uint32_t flags, const int32_t* roi_dev, uint8_t* const* out,
+                                    const uint64_t* capacity, uint64_t* out_size_dev,
+                                    int32_t* status_dev, void* stream);
+
+/*
  * Decompress n RLE1 streams in one launch.
  *   in            host array of n device pointers (16-byte aligned).
  *   in_bytes      host uint64[n]: readable bytes of each stream buffer.

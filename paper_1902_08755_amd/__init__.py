@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
         "cmp_rle_max_size": ([i32, i32, i32], sz),
         "cmp_rle_workspace_size": ([IMG, i32], sz),
         "cmp_rle_compress": ([IMG, i32, i32, ctypes.c_uint32, P, P, P, P, P, P, sz, P], i32),
+        "cmp_rle_compress_noalloc": ([IMG, i32, i32, ctypes.c_uint32, P, P, P, P, P, P], i32),
         "cmp_rle_decompress": ([P, P, i32, IMG, P, P, P], i32),
         "cmp_rle_set_groups_per_cu": ([i32, i32], i32),
         "cmp_rle_set_wait_limit": ([i32], i32),

@@ -38,6 +38,7 @@
 #include <string.h>
 
 #include <atomic>
+#include <mutex>
 
 #include "cmp_internal.hpp"
 
@@ -1121,6 +1122,39 @@ static int64_t rle_flag_count(const cmp_image* imgs, int32_t n) {
   return f;
 }
 
+// Scratch memory of cmp_rle_compress_noalloc: the tickets and look-back
+// flags that cmp_rle_compress keeps in the caller's workspace. Each device
+// holds its own copy until the process ends. Host code never passes this
+// name to a kernel (on the host it is only a stand-in for the symbol): it
+// passes the device address that hipGetSymbolAddress returns for the
+// current device, looked up once per device and kept in g_scratch_ptr.
+static_assert(CMP_RLE_SCRATCH_BYTES == kTicketBytes + 8 * 131072,
+              "the scratch holds the tickets and 131072 look-back flags");
+static __device__ __align__(256) uint8_t scratch[CMP_RLE_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];
+
+// The current device's address of `scratch` (nullptr, with the error set,
+// if it cannot be found).
+static void* scratch_address() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    set_error("no current HIP device (or more than 64 devices)");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error("hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace cmp
 
 using namespace cmp;
@@ -1213,6 +1247,29 @@ extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_for
                      0, s, a);
   CMP_CHECK_HIP(hipGetLastError());
   return CMP_OK;
+}
+
+extern "C" cmp_status cmp_rle_compress_noalloc(const cmp_image* imgs, int32_t n, cmp_format fmt,
+                                               uint32_t flags, const int32_t* roi_dev,
+                                               uint8_t* const* out, const uint64_t* capacity,
+                                               uint64_t* out_size_dev, int32_t* status_dev,
+                                               void* stream) {
+  CMP_REQUIRE(n >= 0 && n <= kRleMax, "n = %d must be 0..%d", n, kRleMax);
+  if (n == 0) return CMP_OK;
+  CMP_REQUIRE(imgs, "imgs is NULL");
+  for (int i = 0; i < n; ++i)
+    CMP_REQUIRE(rect_valid(imgs[i].roi), "imgs[%d] has a negative size", i);
+  const size_t need = cmp_rle_workspace_size(imgs, n);
+  if (need > CMP_RLE_SCRATCH_BYTES) {
+    set_error("these images need %zu bytes of scratch; the static maximum is %zu "
+              "(131072 blocks of 4096 pixels): use cmp_rle_compress with a workspace",
+              need, (size_t)CMP_RLE_SCRATCH_BYTES);
+    return CMP_ENOSPC;
+  }
+  void* ws = scratch_address();
+  if (!ws) return CMP_EHIP;
+  return cmp_rle_compress(imgs, n, fmt, flags, roi_dev, out, capacity, out_size_dev, status_dev,
+                          ws, CMP_RLE_SCRATCH_BYTES, stream);
 }
 
 extern "C" cmp_status cmp_rle_set_wait_limit(int32_t polls) {

@@ -196,3 +196,23 @@ def test_roi_and_rle_argument_errors():
     nb = (ctypes.c_uint64 * 1)(100)
     assert L.cmp_rle_decompress(ins, nb, 1, imgs, None, 0x5000, None) == cmp.CMP_EINVAL
     assert L.cmp_rle_decompress(ins, nb, 1, imgs, None, None, None) == cmp.CMP_EINVAL
+
+
+def test_rle_compress_noalloc_rejects_inputs_beyond_its_scratch():
+    # 131072 blocks of 4096 pixels is the static scratch's limit; 64 images
+    # of 4096x4096 need 262144 (checked on the host, nothing is launched)
+    L = cmp.lib()
+    big = cmp.CImage()
+    big.roi = cmp.Rect(0, 0, 4096, 4096)
+    arr = (cmp.CImage * 64)(*([big] * 64))
+    assert L.cmp_rle_workspace_size(arr, 64) == 8192 + 8 * 262144
+    st = L.cmp_rle_compress_noalloc(arr, 64, cmp.RGBA8, 0, None, None, None, None, None, None)
+    assert st == cmp.CMP_ENOSPC
+    assert "static maximum" in L.cmp_last_error().decode()
+    # n out of range and negative sizes are rejected first
+    assert L.cmp_rle_compress_noalloc(arr, 65, cmp.RGBA8, 0, None, None, None, None, None,
+                                      None) == cmp.CMP_EINVAL
+    bad = cmp.CImage()
+    bad.roi = cmp.Rect(0, 0, -1, 5)
+    assert L.cmp_rle_compress_noalloc((cmp.CImage * 1)(bad), 1, cmp.RGBA8, 0, None, None, None,
+                                      None, None, None) == cmp.CMP_EINVAL
