@@ -349,6 +349,45 @@ cmp_status cmp_rle_decompress(const uint8_t* const* in, const uint64_t* in_bytes
                               void* stream);
 
 /*
+ * Basic 64-bit RLE (Section 5.5.1, Enhanced RLE Compression: the basic
+ * compressor compares two RGBA8 pixels at a time as one 64-bit token, so it
+ * only shortens runs of equal pixel pairs; the per-component codec above is
+ * the thesis's improvement on it). Stream format "RL64" (the thesis gives
+ * none; this library's), all integers little-endian:
+ *   header  magic 0x34364C52, roi.x, roi.y, roi.w, roi.h, nstreams (1:
+ *           colour; 2: colour + depth), 4096, nblocks = ceil(w h / 4096)
+ *   boff[nblocks], size[nblocks][nstreams] (uint32), zero bytes to a
+ *   multiple of 16, then per block its streams back to back, zero-padded to
+ *   a multiple of 16 bytes (the layout of RLE1).
+ * Symbols: the ROI's pixels row-major in pairs, symbol j = pixel 2j (low 32
+ * bits) | pixel 2j+1 (high 32 bits), an odd last pixel of a block paired
+ * with 0; colour words form stream 0, depth words stream 1. A block of len
+ * pixels has m = ceil(len / 2) symbols. Its runs are the maximal runs of
+ * equal symbols that do not cross a multiple of 128 symbols (256 pixels).
+ * A stream with R runs is stored as tokens when align8(R) + 8 R < 8 m: the
+ * R bytes (run length - 1), zero bytes to a multiple of 8, then the R run
+ * values as 64-bit words; otherwise as its m symbols (size == 8 m marks raw).
+ */
+size_t cmp_rle64_max_size(int32_t w, int32_t h, int32_t nstreams);
+
+/* Compress n images to RL64 streams in one launch: the arguments, workspace
+ * (cmp_rle_workspace_size), statuses, ordering and errors of
+ * cmp_rle_compress without its flags; capacity[i] >= cmp_rle64_max_size(w,
+ * h, depth ? 2 : 1). */
+cmp_status cmp_rle64_compress(const cmp_image* imgs, int32_t n, cmp_format fmt,
+                              const int32_t* roi_dev, uint8_t* const* out,
+                              const uint64_t* capacity, uint64_t* out_size_dev,
+                              int32_t* status_dev, void* workspace, size_t ws_bytes, void* stream);
+
+/* Decompress n RL64 streams in one launch: the arguments, statuses and
+ * errors of cmp_rle_decompress (2-stream streams need a depth buffer).
+ * CMP_ECORRUPT also for nonzero padding bytes and a nonzero partner of an
+ * odd last pixel. Not affected by cmp_rle_set_groups_per_cu. */
+cmp_status cmp_rle64_decompress(const uint8_t* const* in, const uint64_t* in_bytes, int32_t n,
+                                const cmp_image* out, int32_t* roi_out_dev, int32_t* status_dev,
+                                void* stream);
+
+/*
  * Occupancy of the RLE kernels, for frames composited asynchronously
  * (Section 5.4: the stages of consecutive frames overlap). Both kernels run
  * a resident grid that by default fills every compute unit; a cap of c

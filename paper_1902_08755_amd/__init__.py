@@ -96,6 +96,9 @@ def lib() -> ctypes.CDLL:
         "cmp_rle_compress": ([IMG, i32, i32, ctypes.c_uint32, P, P, P, P, P, P, sz, P], i32),
         "cmp_rle_compress_noalloc": ([IMG, i32, i32, ctypes.c_uint32, P, P, P, P, P, P], i32),
         "cmp_rle_decompress": ([P, P, i32, IMG, P, P, P], i32),
+        "cmp_rle64_max_size": ([i32, i32, i32], sz),
+        "cmp_rle64_compress": ([IMG, i32, i32, P, P, P, P, P, P, sz, P], i32),
+        "cmp_rle64_decompress": ([P, P, i32, IMG, P, P, P], i32),
         "cmp_rle_set_groups_per_cu": ([i32, i32], i32),
         "cmp_rle_set_wait_limit": ([i32], i32),
         "cmp_batch_plan_create": ([ctypes.POINTER(CJob), i32, ctypes.c_char_p,
@@ -435,6 +438,47 @@ def rle_decompress(streams: Sequence[torch.Tensor], outs: Sequence, stream=None,
     st = lib().cmp_rle_decompress(ins, nbytes, n, arr, roi_out.data_ptr(), status.data_ptr(),
                                   _stream(stream))
     _check(st, "cmp_rle_decompress")
+    return roi_out, status
+
+
+def rle64_compress(images: Sequence, roi_dev=None, stream=None):
+    """Basic 64-bit RLE of n images (cmp_rle64_compress, two pixels per
+    token). Returns (streams, sizes, status) like :func:`rle_compress`."""
+    n = len(images)
+    L = lib()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    arr = _images(images, "u32")
+    caps = [int(L.cmp_rle64_max_size(int(im.roi[2]), int(im.roi[3]),
+                                     2 if im.depth is not None else 1)) for im in images]
+    outs = [torch.empty(c, dtype=torch.uint8, device=dev) for c in caps]
+    out_ptrs = (ctypes.c_void_p * max(1, n))(*[o.data_ptr() for o in outs])
+    cap_arr = (ctypes.c_uint64 * max(1, n))(*caps)
+    sizes = torch.zeros(n, dtype=torch.int64, device=dev)
+    status = torch.zeros(n, dtype=torch.int32, device=dev)
+    ws = workspace("rle64", int(L.cmp_rle_workspace_size(arr, n)))
+    st = L.cmp_rle64_compress(arr, n, RGBA8, _cuda(roi_dev, "roi_dev"), out_ptrs, cap_arr,
+                              sizes.data_ptr(), status.data_ptr(), ws.data_ptr(), ws.numel(),
+                              _stream(stream))
+    _check(st, "cmp_rle64_compress")
+    return outs, sizes, status
+
+
+def rle64_decompress(streams: Sequence[torch.Tensor], outs: Sequence, stream=None, roi_out=None,
+                     status=None):
+    """Decodes n RL64 streams into ``outs`` (cmp_rle64_decompress). Returns
+    (roi_out (n, 4) int32, status (n,) int32) device tensors."""
+    n = len(streams)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    arr = _images(outs, "u32")
+    ins = (ctypes.c_void_p * max(1, n))(*[s.data_ptr() for s in streams])
+    nbytes = (ctypes.c_uint64 * max(1, n))(*[s.numel() for s in streams])
+    if roi_out is None:
+        roi_out = torch.empty((n, 4), dtype=torch.int32, device=dev)
+    if status is None:
+        status = torch.zeros(n, dtype=torch.int32, device=dev)
+    st = lib().cmp_rle64_decompress(ins, nbytes, n, arr, roi_out.data_ptr(), status.data_ptr(),
+                                    _stream(stream))
+    _check(st, "cmp_rle64_decompress")
     return roi_out, status
 
 

@@ -216,3 +216,12 @@ def test_rle_compress_noalloc_rejects_inputs_beyond_its_scratch():
     bad.roi = cmp.Rect(0, 0, -1, 5)
     assert L.cmp_rle_compress_noalloc((cmp.CImage * 1)(bad), 1, cmp.RGBA8, 0, None, None, None,
                                       None, None, None) == cmp.CMP_EINVAL
+
+
+def test_rle64_max_size_matches_oracle():
+    L = cmp.lib()
+    for w, h in [(0, 0), (1, 1), (3, 4), (300, 1), (4097, 1), (64, 64), (4096, 3), (1920, 1080),
+                 (2049, 2)]:
+        for ns in (1, 2):
+            assert L.cmp_rle64_max_size(w, h, ns) == oracle.rle64_max_size(w, h, ns), (w, h, ns)
+    assert L.cmp_rle64_max_size(4, 4, 3) == 0 and L.cmp_rle64_max_size(-1, 4, 1) == 0
