@@ -317,11 +317,19 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
 }
 
 // ---------------------------------------------------------- decompress
-// Exclusive workgroup scan of kW packed words; also returns the totals.
-// `sh` holds 4 * kW words; ends with a barrier.
+// Run-length sums of a block's planes, 21-bit fields, three per word: a
+// plane of < 2048 tokens of <= 256 pixels sums to < 2^21, so no field can
+// overflow into the next, whatever the stream holds.
+__device__ __forceinline__ int fld_word(int k) { return k / 3; }
+__device__ __forceinline__ int fld_shift(int k) { return 21 * (k % 3); }
+constexpr uint64_t kFld = (1u << 21) - 1;
+
+
+// Exclusive workgroup scan with a single barrier: the caller keeps a barrier
+// between these reads of `sh` and its next writes.
 template <int kW>
-__device__ __forceinline__ void block_scan_n(const uint64_t (&v)[kW], uint64_t (&ex)[kW],
-                                             uint64_t (&tot)[kW], uint64_t* sh) {
+__device__ __forceinline__ void block_scan_once(const uint64_t (&v)[kW], uint64_t (&ex)[kW],
+                                                uint64_t (&tot)[kW], uint64_t* sh) {
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   uint64_t inc[kW];
 #pragma unroll
@@ -342,23 +350,36 @@ __device__ __forceinline__ void block_scan_n(const uint64_t (&v)[kW], uint64_t (
     ex[i] = p + inc[i] - v[i];
     tot[i] = t;
   }
-  __syncthreads();
 }
 
-// Run-length sums of a block's planes, 21-bit fields, three per word: a
-// plane of < 2048 tokens of <= 256 pixels sums to < 2^21, so no field can
-// overflow into the next, whatever the stream holds.
-__device__ __forceinline__ int fld_word(int k) { return k / 3; }
-__device__ __forceinline__ int fld_shift(int k) { return 21 * (k % 3); }
-constexpr uint64_t kFld = (1u << 21) - 1;
-
+// 16 bytes at any byte offset `off` of a buffer whose first `end` bytes
+// (end >= 16) may be read: load16_from reads them with one 16-byte load from
+// src = min(off, end - 16); when the bytes run past `end`, load16_fix shifts
+// the 16 bytes that end there into place (bytes past `end` read 0). Split in
+// two so that a lane's loads are all issued before any of them is waited for.
+// Offsets are 32-bit: a stream is smaller than 4 GiB.
+__device__ __forceinline__ u32x4 load16_from(const uint8_t* base, uint32_t src) {
+  u32x4 v;
+  __builtin_memcpy(&v, base + src, 16);
+  return v;
+}
+__device__ __forceinline__ u32x4 load16_fix(u32x4 v, uint32_t src, uint32_t off) {
+  if (src != off) {   // rare: the last bytes of an exactly sized buffer
+    uint32_t d = (uint32_t)(off - src);   // 1..15
+    uint64_t lo = (uint64_t)v.x | ((uint64_t)v.y << 32), hi = (uint64_t)v.z | ((uint64_t)v.w << 32);
+    if (d >= 8) { lo = hi; hi = 0; d -= 8; }
+    if (d) { lo = (lo >> (8 * d)) | (hi << (64 - 8 * d)); hi >>= 8 * d; }
+    v = u32x4{(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)};
+  }
+  return v;
+}
 
 __global__ __launch_bounds__(kThreads, 4) void rle_decompress_kernel(const RleDArgs a) {
-  // the block payload, later the bytes of its runs at their start positions
-  __shared__ __attribute__((aligned(16))) uint8_t stage[kStage];
+  // the bytes of each run-coded plane's runs at their start positions
+  __shared__ __attribute__((aligned(16))) uint8_t vals[8 * kBlock];
   __shared__ __attribute__((aligned(16))) uint32_t starts[8][kBlock / 32];   // run-start bits
   __shared__ uint64_t sh[12];
-  __shared__ int32_t s_bad[kThreads / kWave];
+  __shared__ int32_t s_bad[3];   // a malformed block, in rotation over consecutive slots
   // byte selectors that fill a word from its run starts: for start nibble n,
   // byte j takes the word's byte at the last start <= j, else byte 3 of the
   // previous word (v_perm numbering: 0..3 this word, 4..7 the previous one)
@@ -373,6 +394,8 @@ __global__ __launch_bounds__(kThreads, 4) void rle_decompress_kernel(const RleDA
     }
     fill_sel[tid] = sel;
   }
+  reinterpret_cast<u32x4*>(&starts[0][0])[tid] = u32x4{0, 0, 0, 0};
+  if (tid < 3) s_bad[tid] = 0;
   const int lane = tid % kWave;
 
   // Wave 0 reads and checks the header of stream i in lane i (n <= 64) into
@@ -424,6 +447,7 @@ __global__ __launch_bounds__(kThreads, 4) void rle_decompress_kernel(const RleDA
   __syncthreads();
   const uint32_t total = t_total;
 
+  uint32_t tslot = 0;   // slots with run-coded planes so far (uniform): picks the s_bad entry
   for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
   int tid = threadIdx.x;   // opaque per iteration (see the compressor)
   __asm__ volatile("" : "+v"(tid));
@@ -458,6 +482,8 @@ __global__ __launch_bounds__(kThreads, 4) void rle_decompress_kernel(const RleDA
   const u32x4 s47 = ld_u32x4(srow + (np == 8 ? 4 : 0));
   uint2 bo;   // boff[b], boff[b + 1]: a 4-byte aligned pair
   __builtin_memcpy(&bo, __builtin_assume_aligned(tbl + b, 4), 8);
+  const uint32_t boff = bo.x;
+  const uint32_t bnext = bo.y;   // the first size entry when b is the last block
   uint32_t size[8], poff[8], btotal = 0;
   int e = 0;
 #pragma unroll
@@ -469,11 +495,11 @@ __global__ __launch_bounds__(kThreads, 4) void rle_decompress_kernel(const RleDA
     poff[k] = btotal;
     btotal += size[k];
   }
-  const uint32_t boff = bo.x;
-  const uint32_t bnext = bo.y;   // the first size entry when b is the last block
   if ((boff & 15u) || (b == 0 && boff != 0)) e = CMP_ECORRUPT;
   if ((uint64_t)b + 1 < nb && (uint64_t)bnext != boff + align16(btotal)) e = CMP_ECORRUPT;
-  if (rle_p0(nb, np) + boff + align16(btotal) > I.in_bytes) e = CMP_ECORRUPT;
+  // (a stream smaller than 4 GiB: all its offsets are 32-bit)
+  if (rle_p0(nb, np) + boff + align16(btotal) > imin64((int64_t)I.in_bytes, 0xFFFFFFFFll))
+    e = CMP_ECORRUPT;
   if (e) {   // uniform; no LDS was touched in this slot
     if (tid == 0) a.status[s] = e;
     continue;
@@ -482,99 +508,101 @@ __global__ __launch_bounds__(kThreads, 4) void rle_decompress_kernel(const RleDA
 #pragma unroll
   for (int k = 0; k < 8; ++k)
     if (k < np && size[k] != (uint32_t)len) tokmask |= 1u << k;
-  const uint32_t padded = (uint32_t)align16(btotal);
-  reinterpret_cast<u32x4*>(&starts[0][0])[tid] = u32x4{0, 0, 0, 0};
-  {
-    // the whole block payload to LDS: all loads in flight before the stores
-    const u32x4* src = reinterpret_cast<const u32x4*>(I.in + rle_p0(nb, np) + boff);
-    u32x4* dst = reinterpret_cast<u32x4*>(stage);
-    constexpr int kMaxPer = (8 * kBlock / 16 + kThreads - 1) / kThreads;
-    u32x4 tmp[kMaxPer];
-    const int nvi = (int)(padded / 16);
-#pragma unroll
-    for (int k = 0; k < kMaxPer; ++k)
-      tmp[k] = tid + k * kThreads < nvi ? __builtin_nontemporal_load(&src[tid + k * kThreads]) : u32x4{0, 0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < kMaxPer; ++k)
-      if (tid + k * kThreads < nvi) dst[tid + k * kThreads] = tmp[k];
-  }
-  __syncthreads();
 
-  // Every plane's 16-byte window of this lane: the raw bytes of its 16
-  // pixels, or its 8 tokens (run length - 1, value). A plane starts at any
-  // byte offset (a raw plane of odd length moves the next one), so the
-  // window is 5 aligned words funnel-shifted by 0..3 bytes.
+  // Every plane's 16-byte window of this lane, straight from the stream:
+  // the raw bytes of its 16 pixels, or its tokens (run length - 1, value).
+  // A run-coded plane of T tokens gives each lane tpl = ceil(T / 256) of
+  // them (at most 8), so that all four waves share the scatter below. A lane
+  // without bytes in a plane reads the payload's first bytes.
   const int q0 = tid * kPxPerLane;
-  u32x4 win[8];
+  const uint32_t pay = (uint32_t)(rle_p0(nb, np) + boff);
+  const uint32_t last16 = (uint32_t)imin64((int64_t)I.in_bytes, 0xFFFFFFFFll) - 16u;
+  int tpl[8], nv[8];   // tokens per lane (uniform), this lane's tokens
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    win[k] = u32x4{0, 0, 0, 0};
-    if (k < np) {
-      const uint32_t off = poff[k] + (uint32_t)q0;
-      const uint32_t* w = reinterpret_cast<const uint32_t*>(stage) + (off >> 2);
-      const uint32_t d0 = w[0], d1 = w[1], d2 = w[2], d3 = w[3], d4 = w[4];
-      const uint32_t sb = poff[k] & 3u;
-      win[k] = u32x4{__builtin_amdgcn_alignbyte(d1, d0, sb), __builtin_amdgcn_alignbyte(d2, d1, sb),
-                     __builtin_amdgcn_alignbyte(d3, d2, sb), __builtin_amdgcn_alignbyte(d4, d3, sb)};
-    }
+    const int ntok = (int)(size[k] / 2);
+    tpl[k] = uniform(max(1, (ntok + kThreads - 1) / kThreads));
+    nv[k] = min(tpl[k], max(0, ntok - tid * tpl[k]));
   }
+  u32x4 win[8];
+  uint32_t woff[8], wsrc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const bool tok = (tokmask >> k) & 1u;
+    const uint32_t lo = tok ? 2u * (uint32_t)tpl[k] * (uint32_t)tid : (uint32_t)q0;   // lane's byte
+    const uint32_t base = (uint32_t)uniform((int)(pay + poff[k]));
+    woff[k] = k < np && lo < size[k] ? base + lo : pay;
+    wsrc[k] = min(woff[k], last16);
+    win[k] = load16_from(I.in, wsrc[k]);   // every plane's load, unconditionally
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) win[k] = k < np ? load16_fix(win[k], wsrc[k], woff[k]) : u32x4{0, 0, 0, 0};
   bool bad = false;
   if (tokmask) {   // uniform
+    // this slot's flag; the next one's is cleared now: its last readers (two
+    // such slots ago) have all passed the previous slot's barriers
+    int32_t* bad_flag = &s_bad[tslot % 3];
+    if (tid == 0) s_bad[(tslot + 1) % 3] = 0;
+    ++tslot;
     // start position of this lane's first token in every run-coded plane
     uint64_t v3[3] = {0, 0, 0}, ex3[3], tot3[3];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       if (tokmask & (1u << k)) {
-        const int nv = min(8, max(0, (int)(size[k] / 2) - tid * 8));   // this lane's tokens
         const uint32_t wv[4] = {win[k].x, win[k].y, win[k].z, win[k].w};
-        uint32_t sum = (uint32_t)nv;   // + the (length - 1) bytes of its tokens
+        uint32_t sum = (uint32_t)nv[k];   // + the (length - 1) bytes of its tokens
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const uint32_t keep = (nv > 2 * i ? 0xFFu : 0u) | (nv > 2 * i + 1 ? 0xFF0000u : 0u);
+          const uint32_t keep = (nv[k] > 2 * i ? 0xFFu : 0u) | (nv[k] > 2 * i + 1 ? 0xFF0000u : 0u);
           sum = __builtin_amdgcn_sad_u8(wv[i] & keep, 0u, sum);
         }
         v3[fld_word(k)] |= (uint64_t)sum << fld_shift(k);
       }
     }
-    block_scan_n<3>(v3, ex3, tot3, sh);   // also: every window has been read
-    bool sums_ok = true;
+    block_scan_once<3>(v3, ex3, tot3, sh);
 #pragma unroll
     for (int k = 0; k < 8; ++k)
       if ((tokmask & (1u << k)) && ((tot3[fld_word(k)] >> fld_shift(k)) & kFld) != (uint64_t)len)
-        sums_ok = false;
-    if (!sums_ok) {   // uniform; the last LDS access of this slot was the scan
-      if (tid == 0) a.status[s] = CMP_ECORRUPT;
-      continue;
-    }
-    // each run's value at its start position, and its start bit
+        bad = true;   // uniform
+    // each run's value at its start position, and its start bit; a run must
+    // not cross a multiple of 256 pixels
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       if (tokmask & (1u << k)) {
-        const int nv = min(8, max(0, (int)(size[k] / 2) - tid * 8));
         const uint32_t wv[4] = {win[k].x, win[k].y, win[k].z, win[k].w};
         uint32_t pos = (uint32_t)((ex3[fld_word(k)] >> fld_shift(k)) & kFld);
-        uint8_t* vals = stage + k * kBlock;
+        uint8_t* vk = vals + k * kBlock;
         uint32_t* bits = starts[k];
-        auto put = [&](uint32_t t) {
-          vals[pos] = (uint8_t)(t >> 8);
-          __hip_atomic_fetch_or(&bits[pos >> 5], 1u << (pos & 31), __ATOMIC_RELAXED,
-                                __HIP_MEMORY_SCOPE_WORKGROUP);
-          pos += (t & 0xFFu) + 1u;
-        };
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-          if (j < nv) put(wv[j >> 1] >> (16 * (j & 1)));
+        for (int j = 0; j < 8; ++j) {
+          if (j < nv[k]) {
+            const uint32_t t = wv[j >> 1] >> (16 * (j & 1));
+            const uint32_t rl = (t & 0xFFu) + 1u;
+            if ((pos % kSeg) + rl > (uint32_t)kSeg) bad = true;
+            if (pos < (uint32_t)kBlock) {
+              vk[pos] = (uint8_t)(t >> 8);
+              __hip_atomic_fetch_or(&bits[pos >> 5], 1u << (pos & 31), __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            pos += rl;
+          }
+        }
       }
     }
+    // one vote per wave into this slot's flag, then the barrier that also
+    // publishes the runs
+    if (__ballot(bad) && lane == 0)
+      __hip_atomic_fetch_or(bad_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __syncthreads();
-    // Expand: a pixel takes the value of the last run start at or before it.
-    // Runs never cross a multiple of 256 pixels, so a 256-pixel segment (the
-    // 16 lanes of one DPP row) starts a run, and the value entering a lane
-    // comes from a scan over its row.
+    const bool block_bad = *bad_flag != 0;
+    // Expand (a malformed block skips it): a pixel takes the value of the
+    // last run start at or before it. A 256-pixel segment (the 16 lanes of
+    // one DPP row) starts with a run, so the value entering a lane comes from
+    // a scan over its row.
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      if (tokmask & (1u << k)) {
-        const u32x4 d = *reinterpret_cast<const u32x4*>(stage + k * kBlock + q0);
+      if ((tokmask & (1u << k)) && !block_bad) {
+        const u32x4 d = *reinterpret_cast<const u32x4*>(vals + k * kBlock + q0);
         const uint32_t m = (starts[k][q0 >> 5] >> (q0 & 31)) & 0xFFFFu;
         const uint32_t dv[4] = {d.x, d.y, d.z, d.w};
         const int hb = 31 - __builtin_clz(m | 1u);
@@ -586,7 +614,6 @@ __global__ __launch_bounds__(kThreads, 4) void rle_decompress_kernel(const RleDA
         y = row_shr<2>(x); if (!(x & 0x100u)) x = y;
         y = row_shr<4>(x); if (!(x & 0x100u)) x = y;
         y = row_shr<8>(x); if (!(x & 0x100u)) x = y;
-        if ((tid & 15) == 0 && q0 < len && !(m & 1u)) bad = true;   // a run crosses a segment
         // word by word: each byte from the last start in the word, else the
         // previous word's last byte (the value entering the lane for word 0)
         uint32_t o[4];
@@ -599,62 +626,94 @@ __global__ __launch_bounds__(kThreads, 4) void rle_decompress_kernel(const RleDA
         win[k] = u32x4{o[0], o[1], o[2], o[3]};
       }
     }
+    // clear this slot's start bits: word q0 / 32 is read only by this lane
+    // and its neighbour in the same wave, which have both read it
+    if ((tid & 1) == 0) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (tokmask & (1u << k)) starts[k][q0 >> 5] = 0;
+    }
+    if (block_bad) {   // uniform
+      if (tid == 0) a.status[s] = CMP_ECORRUPT;
+      continue;
+    }
   }
+  // pixels from the planes: byte k of pixel 4 i + j is byte j of plane k's
+  // word i (a 4 x 4 byte transpose per word of colour and of depth)
   uint32_t col[kPxPerLane], dep[kPxPerLane];
 #pragma unroll
-  for (int j = 0; j < kPxPerLane; ++j) {
-    const int sh8 = 8 * (j & 3);
-    const int wj = j >> 2;
-    uint32_t c = 0, dd = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      c |= ((win[k][wj] >> sh8) & 0xFFu) << (8 * k);
-      dd |= ((win[k + 4][wj] >> sh8) & 0xFFu) << (8 * k);
-    }
-    col[j] = c;
-    dep[j] = dd;
-  }
-  // a malformed stream must not be written: one vote per wave, then a
-  // barrier that also ends every LDS access of this slot
-  const uint64_t vote = __ballot(bad);
-  if (lane == 0) s_bad[tid / kWave] = vote != 0;
-  __syncthreads();
-  if (s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3]) {
-    if (tid == 0) a.status[s] = CMP_ECORRUPT;
-    continue;
+  for (int i = 0; i < 4; ++i) {
+    transpose4x4(win[0][i], win[1][i], win[2][i], win[3][i], col[4 * i], col[4 * i + 1],
+                 col[4 * i + 2], col[4 * i + 3]);
+    transpose4x4(win[4][i], win[5][i], win[6][i], win[7][i], dep[4 * i], dep[4 * i + 1],
+                 dep[4 * i + 2], dep[4 * i + 3]);
   }
   if (swizzled) {
 #pragma unroll
     for (int j = 0; j < kPxPerLane; ++j) col[j] = swizzle_bits(col[j]);
   }
-  // ---- write the pixels (row-major over the ROI)
-  if (q0 < len) {
-    // the block's first pixel (uniform), then this lane's by a 32-bit division
+  // ---- write the pixels (row-major over the ROI). A lane holds 16
+  // consecutive pixels, but stores are issued so that consecutive lanes
+  // write consecutive 16-byte quads: the wave's 1024 pixels are restaged
+  // through LDS (the wave's eighth of every plane's run values, which only
+  // this wave reads), and in store v lane i writes pixels 256 v + 4 i .. + 3
+  // of the wave's range (16-byte stores at a 64-byte lane stride cost four
+  // times the memory requests).
+  {
+    const int wave = tid / kWave;
+    uint8_t* wbase = vals + (kBlock / 4) * wave;
+    // lane L's colour at piece L / 16, bytes 64 (L % 16) ..; depth 4 pieces on
+    uint8_t* wl = wbase + (lane / 16) * kBlock + (lane % 16) * 64;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      *reinterpret_cast<u32x4*>(wl + 16 * c) =
+          u32x4{col[4 * c], col[4 * c + 1], col[4 * c + 2], col[4 * c + 3]};
+      if (np == 8)
+        *reinterpret_cast<u32x4*>(wl + 4 * kBlock + 16 * c) =
+            u32x4{dep[4 * c], dep[4 * c + 1], dep[4 * c + 2], dep[4 * c + 3]};
+    }
+    __builtin_amdgcn_wave_barrier();
+    u32x4 cq[4], dq[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      cq[v] = *reinterpret_cast<const u32x4*>(wbase + v * kBlock + 16 * lane);
+      dq[v] = np == 8 ? *reinterpret_cast<const u32x4*>(wbase + (4 + v) * kBlock + 16 * lane)
+                      : u32x4{0, 0, 0, 0};
+    }
+    // the block's first pixel (uniform), then the quad's by a 32-bit division
+    const int qw = (kBlock / 4) * wave + 4 * lane;   // block pixel of store 0
     const int64_t qb = (int64_t)b * kBlock;
     const int yb = uniform((int)(qb / rw)), xb = uniform((int)(qb - (int64_t)yb * rw));
-    const uint32_t xl = (uint32_t)xb + (uint32_t)q0;
+    const uint32_t xl = (uint32_t)xb + (uint32_t)qw;
     const uint32_t dy = xl / (uint32_t)rw;
     int yy = yb + (int)dy, xx = (int)(xl - dy * (uint32_t)rw);
-    const bool fast = (q0 + kPxPerLane <= len) && (xx + kPxPerLane <= rw);
-    if (fast) {
-      const int64_t o = (int64_t)yy * I.pitch + xx;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        st_u32x4(I.color + o + 4 * v,
-                 u32x4{col[4 * v], col[4 * v + 1], col[4 * v + 2], col[4 * v + 3]});
-        if (np == 8)
-          st_u32x4(I.depth + o + 4 * v,
-                   u32x4{dep[4 * v], dep[4 * v + 1], dep[4 * v + 2], dep[4 * v + 3]});
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < kPxPerLane; ++j) {
-        if (q0 + j < len) {
+    for (int v = 0; v < 4; ++v) {
+      const int qq = qw + (kBlock / 16) * v;
+      if (qq < len) {
+        if (qq + 4 <= len && xx + 4 <= rw) {
           const int64_t o = (int64_t)yy * I.pitch + xx;
-          I.color[o] = col[j];
-          if (np == 8) I.depth[o] = dep[j];
-          if (++xx == rw) { xx = 0; ++yy; }
+          st_u32x4(I.color + o, cq[v]);
+          if (np == 8) st_u32x4(I.depth + o, dq[v]);
+        } else {   // a quad at the end of a row or of the block
+          int y2 = yy, x2 = xx;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (qq + j < len) {
+              const int64_t o = (int64_t)y2 * I.pitch + x2;
+              I.color[o] = cq[v][j];
+              if (np == 8) I.depth[o] = dq[v][j];
+              if (++x2 == rw) { x2 = 0; ++y2; }
+            }
+          }
         }
+      }
+      // advance 256 pixels
+      xx += kBlock / 16;
+      if (xx >= rw) {
+        const int d = xx / rw;
+        yy += d;
+        xx -= d * rw;
       }
     }
   }

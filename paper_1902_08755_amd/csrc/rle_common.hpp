@@ -356,6 +356,22 @@ struct RleDArgs {
 };
 static_assert(sizeof(RleDArgs) <= 4096, "kernel arguments must fit in 4 KiB");
 
+// 4 x 4 byte transpose: byte j of o_i is byte i of input j (pixel words to
+// plane words and back). v_perm takes bytes 0..3 from its second operand and
+// 4..7 from its first: two rounds of four.
+__device__ __forceinline__ void transpose4x4(uint32_t a, uint32_t b, uint32_t c, uint32_t d,
+                                             uint32_t& o0, uint32_t& o1, uint32_t& o2,
+                                             uint32_t& o3) {
+  const uint32_t t0 = __builtin_amdgcn_perm(b, a, 0x05010400u);   // a0 b0 a1 b1
+  const uint32_t t1 = __builtin_amdgcn_perm(b, a, 0x07030602u);   // a2 b2 a3 b3
+  const uint32_t t2 = __builtin_amdgcn_perm(d, c, 0x05010400u);   // c0 d0 c1 d1
+  const uint32_t t3 = __builtin_amdgcn_perm(d, c, 0x07030602u);   // c2 d2 c3 d3
+  o0 = __builtin_amdgcn_perm(t2, t0, 0x05040100u);                // a0 b0 c0 d0
+  o1 = __builtin_amdgcn_perm(t2, t0, 0x07060302u);                // a1 b1 c1 d1
+  o2 = __builtin_amdgcn_perm(t3, t1, 0x05040100u);                // a2 b2 c2 d2
+  o3 = __builtin_amdgcn_perm(t3, t1, 0x07060302u);                // a3 b3 c3 d3
+}
+
 // DPP row shift right by D lanes inside rows of 16 lanes; lanes whose source
 // lies outside the row read 0.
 template <int D>
