@@ -97,6 +97,8 @@ def lib():
         L.orc_assemble_pixels.restype = None
         L.orc_roi_grid.argtypes = [i32, P, i32, i32, i64, i32, i32, P]
         L.orc_roi_grid.restype = None
+        L.orc_roi_rects.argtypes = [P, i32, i32, i32, i32, i32, i32, i32, P]
+        L.orc_roi_rects.restype = i32
         _lib = L
     return _lib
 
@@ -399,3 +401,15 @@ def roi_grid(image, cell, mode="depth", w=None, h=None):
     g = np.zeros(((h + ch - 1) // ch, (w + cw - 1) // cw), np.uint8)
     lib().orc_roi_grid(m, _ptr(a), w, h, a.shape[1], cw, ch, _ptr(g))
     return g
+
+
+def roi_rects(grid, cell, w, h, max_rects=64):
+    """Rectangles covering the occupied cells of a roi_grid (Section 5.3, ROI
+    with holes): per row of cells its maximal runs, a run equal to a run of
+    the row above extends that rectangle, others start one; more than
+    max_rects gives the bounding box. List of (x, y, w, h) in pixels."""
+    g = np.ascontiguousarray(np.asarray(grid, dtype=np.uint8))
+    gh, gw = g.shape
+    out = np.zeros(4 * max(1, gw * gh), np.int32)
+    n = lib().orc_roi_rects(_ptr(g), gw, gh, cell[0], cell[1], w, h, max_rects, _ptr(out))
+    return [tuple(int(v) for v in out[4 * k:4 * k + 4]) for k in range(n)]

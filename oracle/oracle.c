@@ -28,6 +28,7 @@
  */
 #include <stdint.h>
 #include <stddef.h>
+#include <stdlib.h>
 #include <string.h>
 
 typedef struct { int32_t x, y, w, h; } orc_rect;
@@ -881,4 +882,69 @@ void orc_roi_grid(int32_t mode, const void* data, int32_t w, int32_t h, int64_t 
             }
             if (full) grid[(y / ch) * gw + (x / cw)] = 1;
         }
+}
+
+/* ------------------------------------------------------------------------ */
+/* ROI with holes as rectangles (Section 5.3, Region of Interest: analysing */
+/* the framebuffer also finds the holes in the rendered area). The thesis   */
+/* says no more; the reading used here: the occupied cells of a cell grid   */
+/* (orc_roi_grid) are covered by disjoint rectangles, built row by row of   */
+/* cells. A row's maximal runs of occupied cells are taken left to right;   */
+/* a run whose first and last cell equal those of a run of the row above    */
+/* extends that run's rectangle by one row, any other run starts a new      */
+/* rectangle. Rectangles are numbered in the order they start. With more    */
+/* than max_rects of them the image gets one rectangle, the bounding box of */
+/* its occupied cells. Rectangles are returned in pixels, clipped to the    */
+/* w x h image: (x, y, w, h) at rects[4 k]. Returns the count.              */
+/* ------------------------------------------------------------------------ */
+int32_t orc_roi_rects(const uint8_t* grid, int32_t gw, int32_t gh, int32_t cw, int32_t ch,
+                      int32_t w, int32_t h, int32_t max_rects, int32_t* rects)
+{
+    /* rectangles in cells: c0, r0, c1, r1 (half-open), at most gw * gh */
+    int32_t n = 0, cap = gw * gh > 0 ? gw * gh : 1;
+    int32_t* rc = (int32_t*)malloc(sizeof(int32_t) * 4 * (size_t)cap);
+    int32_t* above = (int32_t*)malloc(sizeof(int32_t) * (size_t)(gw > 0 ? gw : 1));   /* rect of the run starting at c in the row above, or -1 */
+    int32_t* here = (int32_t*)malloc(sizeof(int32_t) * (size_t)(gw > 0 ? gw : 1));
+    for (int32_t c = 0; c < gw; ++c) above[c] = -1;
+    for (int32_t r = 0; r < gh; ++r) {
+        for (int32_t c = 0; c < gw; ++c) here[c] = -1;
+        int32_t c = 0;
+        while (c < gw) {
+            if (!grid[(int64_t)r * gw + c]) { ++c; continue; }
+            int32_t e = c;
+            while (e < gw && grid[(int64_t)r * gw + e]) ++e;   /* the run is [c, e) */
+            int32_t k = above[c];
+            if (k >= 0 && rc[4 * k + 2] == e) {
+                rc[4 * k + 3] = r + 1;
+            } else {
+                k = n++;
+                rc[4 * k + 0] = c; rc[4 * k + 1] = r; rc[4 * k + 2] = e; rc[4 * k + 3] = r + 1;
+            }
+            here[c] = k;
+            c = e;
+        }
+        int32_t* t = above; above = here; here = t;
+    }
+    int32_t out = n;
+    if (n > max_rects) {
+        /* the bounding box of the occupied cells */
+        int32_t c0 = gw, r0 = gh, c1 = 0, r1 = 0;
+        for (int32_t k = 0; k < n; ++k) {
+            if (rc[4 * k + 0] < c0) c0 = rc[4 * k + 0];
+            if (rc[4 * k + 1] < r0) r0 = rc[4 * k + 1];
+            if (rc[4 * k + 2] > c1) c1 = rc[4 * k + 2];
+            if (rc[4 * k + 3] > r1) r1 = rc[4 * k + 3];
+        }
+        rc[0] = c0; rc[1] = r0; rc[2] = c1; rc[3] = r1;
+        out = 1;
+    }
+    for (int32_t k = 0; k < out; ++k) {
+        const int32_t x0 = rc[4 * k + 0] * cw, y0 = rc[4 * k + 1] * ch;
+        const int32_t x1 = rc[4 * k + 2] * cw < w ? rc[4 * k + 2] * cw : w;
+        const int32_t y1 = rc[4 * k + 3] * ch < h ? rc[4 * k + 3] * ch : h;
+        rects[4 * k + 0] = x0; rects[4 * k + 1] = y0;
+        rects[4 * k + 2] = x1 - x0; rects[4 * k + 3] = y1 - y0;
+    }
+    free(rc); free(above); free(here);
+    return out;
 }
