@@ -247,6 +247,35 @@ cmp_status cmp_roi_grid(const cmp_image* imgs, int32_t n, cmp_format fmt, int32_
                         int32_t cell_h, uint8_t* grid_dev, void* stream);
 
 /*
+ * ROI with holes as rectangles (Section 5.3: the framebuffer analysis also
+ * finds the holes of the rendered area): the occupied cells of each image's
+ * occupancy grid (cmp_roi_grid's layout and cells) covered by disjoint
+ * rectangles, built row by row of cells. A row's maximal runs of occupied
+ * cells are taken left to right; a run with the same first and last cell as
+ * a run of the row above extends that run's rectangle, any other run starts
+ * a new one; rectangles are numbered in the order they start. With more
+ * than max_rects rectangles an image gets one, the bounding box of its
+ * occupied cells.
+ *   imgs[i].roi.w/h   the image size the grid was made for.
+ *   grid_dev          device, the grids of cmp_roi_grid (same cells).
+ *   rects_dev         device int32[n][max_rects][4], 16-byte aligned:
+ *                     image-local (x, y, w, h) in pixels, clipped to the
+ *                     image; rows past an image's count are (0, 0, 0, 0),
+ *                     i.e. empty ROIs. They are ready to be roi_dev of
+ *                     cmp_rle_compress (each image listed max_rects times)
+ *                     and, as placements, of cmp_composite_depth: the
+ *                     rectangles of a frame leave out only cells without
+ *                     data, so compositing them gives the composite of the
+ *                     frames.
+ *   count_dev         device int32[n]: rectangles per image.
+ * max_rects 1..64; a grid row of at most 4096 cells. n <= 64.
+ * Errors: CMP_EINVAL, CMP_EHIP.
+ */
+cmp_status cmp_roi_rects(const cmp_image* imgs, int32_t n, int32_t cell_w, int32_t cell_h,
+                         const uint8_t* grid_dev, int32_t max_rects, int32_t* rects_dev,
+                         int32_t* count_dev, void* stream);
+
+/*
  * Per-component run-length encoding (Section 5.5.1, Enhanced RLE Compression:
  * one RLE stream per component of the pixel, and the image decomposed into
  * sub-images that are compressed in parallel). Stream format "RLE1"; all

@@ -91,6 +91,7 @@ def lib() -> ctypes.CDLL:
         "cmp_roi_workspace_size": ([IMG, i32], sz),
         "cmp_roi_detect": ([IMG, i32, i32, P, P, sz, P], i32),
         "cmp_roi_grid": ([IMG, i32, i32, i32, i32, P, P], i32),
+        "cmp_roi_rects": ([IMG, i32, i32, i32, P, i32, P, P, P], i32),
         "cmp_rle_max_size": ([i32, i32, i32], sz),
         "cmp_rle_workspace_size": ([IMG, i32], sz),
         "cmp_rle_compress": ([IMG, i32, i32, ctypes.c_uint32, P, P, P, P, P, P, sz, P], i32),
@@ -365,6 +366,23 @@ def roi_grid(images: Sequence, cell, fmt: int = RGBA8, stream=None):
         out.append(buf[o:o + gh * gw].view(gh, gw))
         o += gh * gw
     return out
+
+
+def roi_rects(images: Sequence, cell, grids, max_rects: int = 4, stream=None):
+    """ROI with holes (cmp_roi_rects): rectangles covering each image's
+    occupied cells, from the grids of :func:`roi_grid` (same images and
+    cells). Returns (rects int32 (n, max_rects, 4), counts int32 (n,)) on
+    the device; unused rows are empty ROIs."""
+    n = len(images)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    flat = torch.cat([g.reshape(-1) for g in grids]) if n else torch.zeros(1, dtype=torch.uint8, device=dev)
+    rects = torch.zeros((n, max_rects, 4), dtype=torch.int32, device=dev)
+    counts = torch.zeros(n, dtype=torch.int32, device=dev)
+    st = lib().cmp_roi_rects(_images(images, "u32"), n, int(cell[0]), int(cell[1]),
+                             flat.data_ptr(), int(max_rects), rects.data_ptr(), counts.data_ptr(),
+                             _stream(stream))
+    _check(st, "cmp_roi_rects")
+    return rects, counts
 
 
 # -------------------------------------------------------------------- RLE

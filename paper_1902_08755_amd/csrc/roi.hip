@@ -456,3 +456,154 @@ extern "C" cmp_status cmp_roi_grid(const cmp_image* imgs, int32_t n, cmp_format 
   CMP_CHECK_HIP(hipGetLastError());
   return CMP_OK;
 }
+
+namespace cmp {
+
+// --------------------------------------------------------- ROI rectangles
+// cmp_roi_rects: the occupied cells of each image's occupancy grid covered
+// by disjoint rectangles (Section 5.3: the framebuffer analysis also finds
+// the holes of the rendered area), built row by row of cells: a row's
+// maximal runs of occupied cells, left to right; a run with the same first
+// and last cell as a run of the row above extends that run's rectangle,
+// any other run starts a new one; numbered in the order they start. More
+// than max_rects rectangles give one, the bounding box of the occupied
+// cells.
+//
+// One wave per image. A grid row is read as 64-bit ballot words (lane j:
+// column 64 w + j); its runs are walked with bit scans, uniformly over the
+// wave; the run ends of the row above are kept in LDS per start column,
+// tagged with their row so that they never need clearing.
+constexpr int kRectMaxWords = 64;   // grid rows of at most 64 x 64 cells
+constexpr int kRectMax = 64;        // rectangles per image
+
+struct RectArgs {
+  const uint8_t* grid;
+  int32_t* rects;
+  int32_t* count;
+  int64_t goff[kRoiMax];   // first cell of each image's grid
+  int32_t w[kRoiMax], h[kRoiMax];
+  int32_t n, cw, ch, max_rects;
+};
+static_assert(sizeof(RectArgs) <= 4096, "kernel arguments must fit in 4 KiB");
+
+__global__ __launch_bounds__(kWave) void roi_rects_kernel(const RectArgs a) {
+  __shared__ uint64_t row[kRectMaxWords];                 // occupancy of the current row
+  __shared__ int32_t end_above[kRectMaxWords * 64];      // run end by start column (row above)
+  __shared__ int32_t tag_above[kRectMaxWords * 64];      // the row that entry belongs to
+  __shared__ int32_t rect_above[kRectMaxWords * 64];     // its rectangle
+  __shared__ int32_t rc[kRectMax][4];                    // c0, r0, c1, r1 (cells)
+  const int s = blockIdx.x, lane = threadIdx.x;
+  const int W = a.w[s], H = a.h[s];
+  const int gw = W > 0 ? (W + a.cw - 1) / a.cw : 0, gh = H > 0 ? (H + a.ch - 1) / a.ch : 0;
+  const int nw = (gw + 63) / 64;
+  const uint8_t* g = a.grid + a.goff[s];
+  for (int i = lane; i < nw * 64; i += kWave) tag_above[i] = -2;
+  int n = 0;                                   // rectangles started (uniform)
+  int bc0 = gw, br0 = gh, bc1 = 0, br1 = 0;    // bounding box of the occupied cells
+  for (int r = 0; r < gh; ++r) {
+    // the row's occupancy words: all loads issued, then one ballot per word
+    for (int w = 0; w < nw; ++w) {
+      const int c = 64 * w + lane;
+      const bool occ = c < gw && g[(int64_t)r * gw + c] != 0;
+      const uint64_t m = __ballot(occ);
+      if (lane == 0) row[w] = m;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // walk the runs (uniform)
+    uint64_t prev_top = 0;   // bit 63 of the previous word
+    for (int w = 0; w < nw; ++w) {
+      const uint64_t m = row[w];
+      uint64_t starts = m & ~((m << 1) | prev_top);
+      prev_top = m >> 63;
+      while (starts) {
+        const int c0 = 64 * w + (int)__builtin_ctzll(starts);
+        starts &= starts - 1;
+        // the run's end: the first empty column at or after c0
+        int e = gw;
+        for (int w2 = w; w2 < nw; ++w2) {
+          uint64_t z = ~row[w2];
+          if (w2 == w) z &= ~0ull << (c0 & 63);
+          if (z) {
+            e = min(gw, 64 * w2 + (int)__builtin_ctzll(z));
+            break;
+          }
+        }
+        int k = -1;
+        if (tag_above[c0] == r - 1 && end_above[c0] == e) k = rect_above[c0];
+        if (k >= 0) {
+          if (k < kRectMax && lane == 0) rc[k][3] = r + 1;
+        } else {
+          k = n++;
+          if (k < kRectMax && lane == 0) {
+            rc[k][0] = c0; rc[k][1] = r; rc[k][2] = e; rc[k][3] = r + 1;
+          }
+        }
+        bc0 = min(bc0, c0); bc1 = max(bc1, e);
+        br0 = min(br0, r); br1 = r + 1;
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {   // this row's entry, read when the next row is walked
+          tag_above[c0] = r;
+          end_above[c0] = e;
+          rect_above[c0] = k;
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __builtin_amdgcn_wave_barrier();
+  // out: pixels, clipped; the bounding box when there are too many
+  const int out = n > a.max_rects ? 1 : n;
+  int32_t* dst = a.rects + (int64_t)s * a.max_rects * 4;
+  for (int k = lane; k < a.max_rects; k += kWave) {
+    int4 v = int4{0, 0, 0, 0};
+    if (k < out) {
+      const int c0 = n > a.max_rects ? bc0 : rc[k][0], r0 = n > a.max_rects ? br0 : rc[k][1];
+      const int c1 = n > a.max_rects ? bc1 : rc[k][2], r1 = n > a.max_rects ? br1 : rc[k][3];
+      const int x0 = c0 * a.cw, y0 = r0 * a.ch;
+      v = int4{x0, y0, min(c1 * a.cw, W) - x0, min(r1 * a.ch, H) - y0};
+    }
+    reinterpret_cast<int4*>(dst)[k] = v;
+  }
+  if (lane == 0) a.count[s] = out;
+}
+
+}  // namespace cmp
+
+extern "C" cmp_status cmp_roi_rects(const cmp_image* imgs, int32_t n, int32_t cell_w,
+                                    int32_t cell_h, const uint8_t* grid_dev, int32_t max_rects,
+                                    int32_t* rects_dev, int32_t* count_dev, void* stream) {
+  using namespace cmp;
+  CMP_REQUIRE(n >= 0 && n <= kRoiMax, "n = %d must be 0..%d", n, kRoiMax);
+  if (n == 0) return CMP_OK;
+  CMP_REQUIRE(imgs && grid_dev && rects_dev && count_dev, "NULL argument");
+  CMP_REQUIRE(cell_w >= 1 && cell_h >= 1, "cells must be at least 1x1");
+  CMP_REQUIRE(max_rects >= 1 && max_rects <= kRectMax, "max_rects = %d must be 1..%d", max_rects,
+              kRectMax);
+  CMP_REQUIRE(((uintptr_t)rects_dev & 15) == 0 && ((uintptr_t)count_dev & 3) == 0,
+              "rects_dev must be 16-byte and count_dev 4-byte aligned");
+  RectArgs a;
+  memset(&a, 0, sizeof a);
+  int64_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    CMP_REQUIRE(rect_valid(imgs[i].roi), "imgs[%d] has a negative size", i);
+    const int W = rect_empty(imgs[i].roi) ? 0 : imgs[i].roi.w;
+    const int H = rect_empty(imgs[i].roi) ? 0 : imgs[i].roi.h;
+    const int64_t gw = W ? (W + cell_w - 1) / cell_w : 0, gh = H ? (H + cell_h - 1) / cell_h : 0;
+    CMP_REQUIRE(gw <= 64 * kRectMaxWords, "imgs[%d]: %lld cells per row; at most %d", i,
+                (long long)gw, 64 * kRectMaxWords);
+    a.goff[i] = off;
+    a.w[i] = W;
+    a.h[i] = H;
+    off += gw * gh;
+  }
+  a.grid = grid_dev;
+  a.rects = rects_dev;
+  a.count = count_dev;
+  a.n = n;
+  a.cw = cell_w;
+  a.ch = cell_h;
+  a.max_rects = max_rects;
+  hipLaunchKernelGGL(roi_rects_kernel, dim3((unsigned)n), dim3(kWave), 0, (hipStream_t)stream, a);
+  CMP_CHECK_HIP(hipGetLastError());
+  return CMP_OK;
+}
