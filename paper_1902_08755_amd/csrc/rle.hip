@@ -71,6 +71,10 @@ __device__ __forceinline__ void emit_tokens(uint8_t* stage, uint32_t off, uint32
   }
 }
 
+// kSwizzle: the colour words are bit-swizzled before their planes are taken
+// (a template parameter, so that the plain kernel carries no branch and no
+// copies of the pixel registers for it).
+template <bool kSwizzle>
 __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t stage[kStage];
   __shared__ uint32_t sh[16];
@@ -145,14 +149,14 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
       }
       if (tid < 8) {
         const uint32_t hdr[8] = {kRleMagic, (uint32_t)rx, (uint32_t)ry, 0u, 0u,
-                                 (uint32_t)np | (a.swizzle ? 0x100u : 0u), (uint32_t)kBlock, 0u};
+                                 (uint32_t)np | (kSwizzle ? 0x100u : 0u), (uint32_t)kBlock, 0u};
         reinterpret_cast<uint32_t*>(out)[tid] = hdr[tid];
       }
       if (tid == 0) a.out_size[s] = 32;
     } else {
       const int len = (int)imin64(kBlock, npx - (int64_t)b * kBlock);
       const int q0 = tid * kPxPerLane;   // block-relative first pixel
-      if (a.swizzle) {
+      if (kSwizzle) {
 #pragma unroll
         for (int j = 0; j < kPxPerLane; ++j) col[j] = swizzle_bits(col[j]);
       }
@@ -296,7 +300,7 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
       if (b == 0) {
         if (tid < 8) {
           const uint32_t hdr[8] = {kRleMagic, (uint32_t)rx, (uint32_t)ry, (uint32_t)rw,
-                                   (uint32_t)rh, (uint32_t)np | (a.swizzle ? 0x100u : 0u),
+                                   (uint32_t)rh, (uint32_t)np | (kSwizzle ? 0x100u : 0u),
                                    (uint32_t)kBlock, (uint32_t)nb};
           reinterpret_cast<uint32_t*>(out)[tid] = hdr[tid];
         }
@@ -908,10 +912,14 @@ extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_for
   if (st != CMP_OK) return st;
   a.swizzle = (flags & CMP_RLE_SWIZZLE) ? 1 : 0;
   // one wave of workgroups at most: more would find the tickets drawn
-  const int64_t cap = resident_groups((const void*)rle_compress_kernel, g_compress_groups,
+  // (both instances have the same resources, so one occupancy serves both)
+  const int64_t cap = resident_groups((const void*)rle_compress_kernel<false>, g_compress_groups,
                                       rle_compress_cap());
-  hipLaunchKernelGGL(rle_compress_kernel, dim3((unsigned)(grid < cap ? grid : cap)), dim3(kThreads),
-                     0, s, a);
+  const dim3 grid_dim((unsigned)(grid < cap ? grid : cap));
+  if (a.swizzle)
+    hipLaunchKernelGGL(rle_compress_kernel<true>, grid_dim, dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(rle_compress_kernel<false>, grid_dim, dim3(kThreads), 0, s, a);
   CMP_CHECK_HIP(hipGetLastError());
   return CMP_OK;
 }
