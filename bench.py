@@ -345,6 +345,85 @@ def bench_over(dev, dtype, reps=10):
 EXTRAS_ONLY = ("over_fp32", "over_fp16", "over_backward", "batch")
 
 
+def bench_codecs(frames, s_obj, reps=50):
+    """The compressor family of Section 5.5.1 on the 16 x 1920x1080 frames
+    with their device ROIs: stream bytes of per-component RLE, swizzled
+    per-component RLE and the basic 64-bit two-pixel RLE (space saved
+    against the raw ROI bytes), and the RL64 kernels' times (each launched
+    `reps` times back to back over the buffer copies)."""
+    s = s_obj.cuda_stream
+    f0 = frames[0]
+    rois = [tuple(r) for r in f0.roi.cpu().tolist()]
+    raw = sum(8 * w * h for _, _, w, h in rois)
+    rle1 = int(f0.rle.sizes.sum())
+    _, sw, _ = cmp.rle_compress(f0.images, roi_dev=f0.roi, swizzle=True)
+    out = {"raw_roi_bytes": raw}
+    # RL64: one set of streams and decoded blocks per buffer copy
+    L = cmp.lib()
+    per = []
+    for f in frames:
+        caps = [int(L.cmp_rle64_max_size(1920, 1080, 2))] * 16
+        outs = [torch.empty(c, dtype=torch.uint8, device=f.roi.device) for c in caps]
+        ptrs = (ctypes.c_void_p * 16)(*[o.data_ptr() for o in outs])
+        cap_arr = (ctypes.c_uint64 * 16)(*caps)
+        sizes = torch.zeros(16, dtype=torch.int64, device=f.roi.device)
+        status = torch.zeros(16, dtype=torch.int32, device=f.roi.device)
+        ws = torch.zeros(L.cmp_rle_workspace_size(f.img_arr, 16), dtype=torch.uint8,
+                         device=f.roi.device)
+        dec_bytes = (ctypes.c_uint64 * 16)(*caps)
+        per.append((f, outs, ptrs, cap_arr, sizes, status, ws, dec_bytes))
+
+    def comp(p):
+        f, outs, ptrs, cap_arr, sizes, status, ws, _ = p
+        st = L.cmp_rle64_compress(f.img_arr, 16, cmp.RGBA8, f.roi.data_ptr(), ptrs, cap_arr,
+                                  sizes.data_ptr(), status.data_ptr(), ws.data_ptr(), ws.numel(), s)
+        assert st == 0, L.cmp_last_error().decode()
+
+    def decomp(p):
+        f, outs, ptrs, cap_arr, sizes, status, ws, dec_bytes = p
+        st = L.cmp_rle64_decompress(ptrs, dec_bytes, 16, f.dec_out, f.roi_dec.data_ptr(),
+                                    f.status.data_ptr(), s)
+        assert st == 0, L.cmp_last_error().decode()
+
+    res = {}
+    for name, fn in (("rl64_compress", comp), ("rl64_decompress", decomp)):
+        for i in range(len(per)):
+            fn(per[i])
+        t0, t1 = DevEvent(), DevEvent()
+        torch.cuda.synchronize()
+        t0.record(s)
+        for i in range(reps):
+            fn(per[i % len(per)])
+        t1.record(s)
+        torch.cuda.synchronize()
+        res[name] = t0.elapsed_ms(t1) / reps * 1e3
+    torch.cuda.synchronize()
+    # the RL64 round trip must give the frames' ROIs back, with clean statuses
+    for p in per:
+        assert int(p[5].abs().sum()) == 0 and int(p[0].status.abs().sum()) == 0
+    rl64 = int(per[0][4].sum())
+    for name, b in (("rle1_per_component", rle1), ("rle1_swizzled", int(sw.sum())),
+                    ("rl64_two_pixel", rl64)):
+        out[name] = {"bytes": b, "saved": 1 - b / raw}
+    roi_px = raw // 8
+    for name in ("rl64_compress", "rl64_decompress"):
+        out[name] = {"us": res[name], "GBps": (8 * roi_px + rl64) / res[name] / 1e3}
+    return out
+
+
+def read_error_summary(path):
+    """`key: value` lines of the committed over-error summary (the parity
+    test's full-frame comparison with the FP64 oracle), or None."""
+    if not os.path.exists(path):
+        return None
+    out = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            out[k.strip()] = v.strip()
+    return out
+
+
 def bench_backward(dev, reps=10, which=("forward", "backward", "forward_backward")):
     ow = synth.over_bricks(seed=4, n=32, W=1024, H=1024, device=dev, with_target=True)
     imgs = ow.layers
@@ -477,7 +556,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default="", help="profile helper: run only this stage (or probe_copy, a 1 GiB copy; "
-                    "or an extra: over_fp32, over_fp16, over_backward, batch) repeatedly")
+                    "or an extra: over_fp32, over_fp16, over_backward, batch, rle64) repeatedly")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
@@ -532,6 +611,12 @@ def main():
     abytes, roi_px = algorithmic_bytes(frames[0], rois, sizes)
     ref_color = frames[0].out_c.clone()   # every copy holds the same workload
 
+    if args.only == "rle64":
+        # profile helper: the RL64 kernels, `steps` launches each
+        r = bench_codecs(frames, s_obj, reps=args.steps)
+        log(f"ran rl64 compress and decompress {args.steps} times each")
+        print(json.dumps({"only": args.only, **r}))
+        return
     if args.only:
         k = STAGES.index(args.only)
         for i in range(args.steps):
@@ -624,6 +709,11 @@ def main():
         ex["over_grad_32x1024x1024"] = bench_backward(dev)
         ex["batch_256_jobs"] = bench_batch(dev, tune_path=os.path.join(
             os.environ.get("TMPDIR", "/tmp"), "cmp_tune_cache.txt"))
+        ex["codecs_16x1920x1080"] = bench_codecs(frames, s_obj)
+        err = read_error_summary(os.path.join(ROOT, "profiles", "over_error_64x3840x2160.txt"))
+        if err:
+            ex["over_fp32_64x3840x2160"]["rel_err"] = {k[5:]: v for k, v in err.items() if k.startswith("fp32_")}
+            ex["over_fp16_64x3840x2160"]["rel_err"] = {k[5:]: v for k, v in err.items() if k.startswith("fp16_")}
         result["extras"] = ex
     if not args.no_cpu:
         log("cpu baseline: the oracle chain on one full frame")
