@@ -128,6 +128,23 @@ cmp_status cmp_composite_depth(const cmp_image* in, int32_t n, const int32_t* ro
                                void* stream);
 
 /*
+ * cmp_composite_depth with the device rectangles cropping the contributors
+ * instead of placing them: in[i] stays where in[i].roi places it (e.g. a
+ * whole frame at its viewport), and only its part inside roi_dev[i] (e.g.
+ * its detected ROI, in destination pixels) is read. Section 5.3: the input
+ * frame places the pixel data at the ROI's position; a frame whose ROI
+ * blocks were decompressed into place (cmp_rle_decompress_at_roi) is read
+ * at its own columns, so a contributor row starts where the destination's
+ * does (whole cache lines when the frame's pitch and the tiles are aligned).
+ * roi_dev is required; other arguments, results and errors as
+ * cmp_composite_depth.
+ */
+cmp_status cmp_composite_depth_crop(const cmp_image* in, int32_t n, const int32_t* roi_dev,
+                                    cmp_rect viewport, uint32_t* out_color, uint32_t* out_depth,
+                                    int64_t out_pitch, cmp_schedule sched, cmp_tile tile,
+                                    void* stream);
+
+/*
  * Ordered (spatial) sort-last compositing with alpha blending.
  * Section 5.2.1: the partial images of convex regions are sorted by depth and
  * blended in order; ordering is the application's part (Section 3.6,
@@ -415,6 +432,18 @@ cmp_status cmp_rle64_compress(const cmp_image* imgs, int32_t n, cmp_format fmt,
 cmp_status cmp_rle64_decompress(const uint8_t* const* in, const uint64_t* in_bytes, int32_t n,
                                 const cmp_image* out, int32_t* roi_out_dev, int32_t* status_dev,
                                 void* stream);
+
+/*
+ * cmp_rle_decompress into frames: out[i] is a whole frame (colour and depth
+ * pointers at its pixel (0, 0), pitch, out[i].roi.w/h its size), and stream
+ * i's ROI block is written at the ROI's position in it (Section 5.3: the
+ * input frame places the pixel data where the ROI says). CMP_ENOSPC (status)
+ * when the ROI does not lie inside the frame. Other arguments, results and
+ * errors as cmp_rle_decompress.
+ */
+cmp_status cmp_rle_decompress_at_roi(const uint8_t* const* in, const uint64_t* in_bytes,
+                                     int32_t n, const cmp_image* out, int32_t* roi_out_dev,
+                                     int32_t* status_dev, void* stream);
 
 /*
  * Occupancy of the RLE kernels, for frames composited asynchronously

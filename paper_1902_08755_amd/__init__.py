@@ -83,6 +83,7 @@ def lib() -> ctypes.CDLL:
         "cmp_last_error": ([], ctypes.c_char_p),
         "cmp_schedule_regions": ([Schedule, Rect, ctypes.POINTER(Rect), i32], i32),
         "cmp_composite_depth": ([IMG, i32, P, Rect, P, P, i64, Schedule, Tile, P], i32),
+        "cmp_composite_depth_crop": ([IMG, i32, P, Rect, P, P, i64, Schedule, Tile, P], i32),
         "cmp_composite_average": ([IMG, i32, Rect, P, i64, Schedule, Tile, P], i32),
         "cmp_assemble_pixels": ([IMG, i32, P, i32, i32, Rect, P, i64, P], i32),
         "cmp_composite_over": ([IMG, i32, i32, P, Rect, P, i64, Schedule, Tile, P], i32),
@@ -97,6 +98,7 @@ def lib() -> ctypes.CDLL:
         "cmp_rle_compress": ([IMG, i32, i32, ctypes.c_uint32, P, P, P, P, P, P, sz, P], i32),
         "cmp_rle_compress_noalloc": ([IMG, i32, i32, ctypes.c_uint32, P, P, P, P, P, P], i32),
         "cmp_rle_decompress": ([P, P, i32, IMG, P, P, P], i32),
+        "cmp_rle_decompress_at_roi": ([P, P, i32, IMG, P, P, P], i32),
         "cmp_rle64_max_size": ([i32, i32, i32], sz),
         "cmp_rle64_compress": ([IMG, i32, i32, P, P, P, P, P, P, sz, P], i32),
         "cmp_rle64_decompress": ([P, P, i32, IMG, P, P, P], i32),
@@ -196,8 +198,9 @@ def _schedule(schedule) -> Schedule:
 
 # ------------------------------------------------------------ compositing
 def composite_depth(images: Sequence, viewport, out_color=None, out_depth=None, roi_dev=None,
-                    schedule=("seq", 1), tile=(0, 0), want_depth=True, stream=None):
-    """Depth-sorted sort-last compositing (cmp_composite_depth)."""
+                    schedule=("seq", 1), tile=(0, 0), want_depth=True, stream=None, crop=False):
+    """Depth-sorted sort-last compositing (cmp_composite_depth; with
+    crop=True cmp_composite_depth_crop: roi_dev crops the placed images)."""
     x, y, w, h = viewport
     dev = torch.device("cuda", torch.cuda.current_device())
     if out_color is None:
@@ -208,10 +211,11 @@ def composite_depth(images: Sequence, viewport, out_color=None, out_depth=None, 
     if out_depth is not None and _u32_pitch(out_depth) != pitch:
         raise ValueError("out_color and out_depth pitches differ")
     arr = _images(images, "u32")
-    st = lib().cmp_composite_depth(arr, len(images), _cuda(roi_dev, "roi_dev"), _rect(viewport),
-                                   out_color.data_ptr(), _cuda(out_depth, "out_depth"), pitch,
-                                   _schedule(schedule), Tile(*tile), _stream(stream))
-    _check(st, "cmp_composite_depth")
+    fn = lib().cmp_composite_depth_crop if crop else lib().cmp_composite_depth
+    st = fn(arr, len(images), _cuda(roi_dev, "roi_dev"), _rect(viewport), out_color.data_ptr(),
+            _cuda(out_depth, "out_depth"), pitch, _schedule(schedule), Tile(*tile),
+            _stream(stream))
+    _check(st, "cmp_composite_depth_crop" if crop else "cmp_composite_depth")
     return out_color, out_depth
 
 
@@ -441,9 +445,11 @@ def rle_set_groups_per_cu(compress: int, decompress: int) -> None:
 
 
 def rle_decompress(streams: Sequence[torch.Tensor], outs: Sequence, stream=None, roi_out=None,
-                   status=None):
+                   status=None, at_roi=False):
     """Decodes n RLE1 streams into ``outs`` (Image-like; roi w/h bound the
-    size). Returns (roi_out (n, 4) int32, status (n,) int32) device tensors."""
+    size): at their top left, or with at_roi=True (cmp_rle_decompress_at_roi)
+    at the ROI's position in each frame. Returns (roi_out (n, 4) int32,
+    status (n,) int32) device tensors."""
     n = len(streams)
     dev = torch.device("cuda", torch.cuda.current_device())
     arr = _images(outs, "u32")
@@ -453,8 +459,8 @@ def rle_decompress(streams: Sequence[torch.Tensor], outs: Sequence, stream=None,
         roi_out = torch.empty((n, 4), dtype=torch.int32, device=dev)
     if status is None:
         status = torch.zeros(n, dtype=torch.int32, device=dev)
-    st = lib().cmp_rle_decompress(ins, nbytes, n, arr, roi_out.data_ptr(), status.data_ptr(),
-                                  _stream(stream))
+    fn = lib().cmp_rle_decompress_at_roi if at_roi else lib().cmp_rle_decompress
+    st = fn(ins, nbytes, n, arr, roi_out.data_ptr(), status.data_ptr(), _stream(stream))
     _check(st, "cmp_rle_decompress")
     return roi_out, status
 

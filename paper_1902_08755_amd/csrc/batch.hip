@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(const BatchArgs a) {
       for (int c0 = 0; c0 < jn || c0 == 0; c0 += kPlaceMax) {
         const int cn = min(kPlaceMax, jn - c0);
         if (c0 > 0) __syncthreads();   // the previous chunk's records are no longer read
-        stage_contributors(DepthSrc{a.ddesc + J.desc_off + c0, nullptr, 0}, cn, s_rec);
+        stage_contributors(DepthSrc{a.ddesc + J.desc_off + c0, nullptr, 0, 0}, cn, s_rec);
         for (int tile = uniform(I.tile0); tile < t1; ++tile) {
           const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
           const int x0 = J.vx + tx * J.tile_w, y0 = J.vy + ty * J.tile_h;

@@ -22,6 +22,7 @@ struct DepthArgs {
   int32_t tile_w, tile_h;
   int32_t accumulate;
   int32_t index_base;
+  int32_t crop;   // roi_dev crops the placed contributors (else it places them)
 };
 static_assert(sizeof(DepthArgs) <= 4096, "kernel arguments must fit in 4 KiB");
 
@@ -43,7 +44,7 @@ __device__ __forceinline__ void tile_of_block(const Region* reg, int nreg, int t
 __global__ __launch_bounds__(kThreads) void depth_kernel(const DepthArgs a) {
   int x0, y0, tw, th;
   tile_of_block(a.reg, a.nreg, a.tile_w, a.tile_h, x0, y0, tw, th);
-  const DepthSrc src{a.c, a.roi_dev, a.index_base};
+  const DepthSrc src{a.c, a.roi_dev, a.index_base, a.crop};
   __shared__ DepthRec s_rec[kPlaceMax];
   stage_contributors(src, a.n, s_rec);   // a.n <= kDepthPerPass <= kPlaceMax
   depth_tile(s_rec, a.n, x0, y0, tw, th, a.out_color, a.out_depth, a.out_pitch, a.vx, a.vy,
@@ -71,10 +72,10 @@ cmp_status validate_depth_inputs(const cmp_image* in, int32_t n) {
 
 using namespace cmp;
 
-extern "C" cmp_status cmp_composite_depth(const cmp_image* in, int32_t n, const int32_t* roi_dev,
-                                          cmp_rect viewport, uint32_t* out_color,
-                                          uint32_t* out_depth, int64_t out_pitch,
-                                          cmp_schedule sched, cmp_tile tile, void* stream) {
+static cmp_status composite_depth_impl(const cmp_image* in, int32_t n, const int32_t* roi_dev,
+                                       bool crop, cmp_rect viewport, uint32_t* out_color,
+                                       uint32_t* out_depth, int64_t out_pitch,
+                                       cmp_schedule sched, cmp_tile tile, void* stream) {
   cmp_status st = validate_depth_inputs(in, n);
   if (st != CMP_OK) return st;
   CMP_REQUIRE(rect_valid(viewport), "viewport has a negative size");
@@ -99,6 +100,7 @@ extern "C" cmp_status cmp_composite_depth(const cmp_image* in, int32_t n, const 
   if (nreg < 0) return nreg;
   CMP_REQUIRE(tiles < (1ll << 24), "too many tiles (%lld)", (long long)tiles);
   a.roi_dev = roi_dev;
+  a.crop = crop ? 1 : 0;
   a.out_color = out_color;
   a.out_depth = out_depth;
   a.out_pitch = out_pitch;
@@ -125,4 +127,22 @@ extern "C" cmp_status cmp_composite_depth(const cmp_image* in, int32_t n, const 
     base += cnt;
   } while (base < n);
   return CMP_OK;
+}
+
+extern "C" cmp_status cmp_composite_depth(const cmp_image* in, int32_t n, const int32_t* roi_dev,
+                                          cmp_rect viewport, uint32_t* out_color,
+                                          uint32_t* out_depth, int64_t out_pitch,
+                                          cmp_schedule sched, cmp_tile tile, void* stream) {
+  return composite_depth_impl(in, n, roi_dev, false, viewport, out_color, out_depth, out_pitch,
+                              sched, tile, stream);
+}
+
+extern "C" cmp_status cmp_composite_depth_crop(const cmp_image* in, int32_t n,
+                                               const int32_t* roi_dev, cmp_rect viewport,
+                                               uint32_t* out_color, uint32_t* out_depth,
+                                               int64_t out_pitch, cmp_schedule sched,
+                                               cmp_tile tile, void* stream) {
+  CMP_REQUIRE(roi_dev, "roi_dev is required");
+  return composite_depth_impl(in, n, roi_dev, true, viewport, out_color, out_depth, out_pitch,
+                              sched, tile, stream);
 }

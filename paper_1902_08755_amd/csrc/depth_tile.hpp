@@ -28,11 +28,14 @@ struct DepthDesc {
   int32_t x, y, w, h;   // placement (host rectangle; bounds the buffer)
 };
 
-// Source of contributor descriptors; `roi_dev` may override placements.
+// Source of contributor descriptors; `roi_dev` may override placements
+// (crop == 0) or crop the contributors to the rectangles that hold their
+// data (crop == 1: the buffers stay where the descriptors place them).
 struct DepthSrc {
   const DepthDesc* d;
   const int32_t* roi_dev;   // device int32[n][4] or nullptr
   int index_base;           // row of roi_dev that corresponds to d[0]
+  int crop;
 };
 
 // Composites the tile [x0, x0+tw) x [y0, y0+th) (destination pixels) of a
@@ -60,7 +63,21 @@ __device__ __forceinline__ void stage_contributors(const DepthSrc& src, int n, D
   for (int i = threadIdx.x; i < n; i += kThreads) {
     const DepthDesc& D = src.d[i];
     DepthRec r{D.x, D.y, D.w, D.h, D.depth, D.color, D.pitch};
-    if (src.roi_dev) {
+    if (src.roi_dev && src.crop) {
+      // the part of the placed buffer inside the device rectangle
+      const int4 q = reinterpret_cast<const int4*>(src.roi_dev)[src.index_base + i];
+      const int x0 = max(q.x, D.x), y0 = max(q.y, D.y);
+      const int x1 = min(q.x + max(q.z, 0), D.x + D.w), y1 = min(q.y + max(q.w, 0), D.y + D.h);
+      r.x = x0;
+      r.y = y0;
+      r.w = max(0, x1 - x0);
+      r.h = max(0, y1 - y0);
+      if (r.w > 0 && r.h > 0) {
+        const int64_t o = (int64_t)(y0 - D.y) * D.pitch + (x0 - D.x);
+        r.depth = D.depth + o;
+        r.color = D.color + o;
+      }
+    } else if (src.roi_dev) {
       const int4 q = reinterpret_cast<const int4*>(src.roi_dev)[src.index_base + i];
       r.x = q.x;
       r.y = q.y;

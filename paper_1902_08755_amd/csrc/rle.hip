@@ -430,7 +430,11 @@ __global__ __launch_bounds__(kThreads, 4) void rle_decompress_kernel(const RleDA
           lerr = CMP_ECORRUPT;
         else if (I.in_bytes < rle_p0(lh[7], (int)np))
           lerr = CMP_ECORRUPT;
-        else if (w > I.cap_w || hh > I.cap_h || (np == 8 && !I.depth))
+        else if ((np == 8 && !I.depth) ||
+                 (a.at_roi ? (int32_t)lh[1] < 0 || (int32_t)lh[2] < 0 ||
+                                 (int64_t)(int32_t)lh[1] + w > I.cap_w ||
+                                 (int64_t)(int32_t)lh[2] + hh > I.cap_h
+                           : w > I.cap_w || hh > I.cap_h))
           lerr = CMP_ENOSPC;
       }
       lslots = (lerr || lh[7] == 0) ? 1u : lh[7];
@@ -686,6 +690,10 @@ __global__ __launch_bounds__(kThreads, 4) void rle_decompress_kernel(const RleDA
     }
     // the block's first pixel (uniform), then the quad's by a 32-bit division
     const int qw = (kBlock / 4) * wave + 4 * lane;   // block pixel of store 0
+    // the block's origin: the frame's top left, or its ROI's position there
+    const int64_t org = a.at_roi ? (int64_t)(int32_t)h[2] * I.pitch + (int32_t)h[1] : 0;
+    uint32_t* const ocol = I.color + org;
+    uint32_t* const odep = np == 8 ? I.depth + org : nullptr;
     const int64_t qb = (int64_t)b * kBlock;
     const int yb = uniform((int)(qb / rw)), xb = uniform((int)(qb - (int64_t)yb * rw));
     const uint32_t xl = (uint32_t)xb + (uint32_t)qw;
@@ -697,16 +705,16 @@ __global__ __launch_bounds__(kThreads, 4) void rle_decompress_kernel(const RleDA
       if (qq < len) {
         if (qq + 4 <= len && xx + 4 <= rw) {
           const int64_t o = (int64_t)yy * I.pitch + xx;
-          st_u32x4(I.color + o, cq[v]);
-          if (np == 8) st_u32x4(I.depth + o, dq[v]);
+          st_u32x4(ocol + o, cq[v]);
+          if (np == 8) st_u32x4(odep + o, dq[v]);
         } else {   // a quad at the end of a row or of the block
           int y2 = yy, x2 = xx;
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             if (qq + j < len) {
               const int64_t o = (int64_t)y2 * I.pitch + x2;
-              I.color[o] = cq[v][j];
-              if (np == 8) I.depth[o] = dq[v][j];
+              ocol[o] = cq[v][j];
+              if (np == 8) odep[o] = dq[v][j];
               if (++x2 == rw) { x2 = 0; ++y2; }
             }
           }
@@ -959,9 +967,9 @@ extern "C" cmp_status cmp_rle_set_groups_per_cu(int32_t compress, int32_t decomp
   return CMP_OK;
 }
 
-extern "C" cmp_status cmp_rle_decompress(const uint8_t* const* in, const uint64_t* in_bytes,
-                                         int32_t n, const cmp_image* out, int32_t* roi_out_dev,
-                                         int32_t* status_dev, void* stream) {
+static cmp_status rle_decompress_impl(const uint8_t* const* in, const uint64_t* in_bytes,
+                                      int32_t n, const cmp_image* out, int32_t* roi_out_dev,
+                                      int32_t* status_dev, bool at_roi, void* stream) {
   CMP_REQUIRE(n >= 0 && n <= kRleMax, "n = %d must be 0..%d", n, kRleMax);
   if (n == 0) return CMP_OK;
   CMP_REQUIRE(in && in_bytes && out && status_dev, "NULL argument");
@@ -988,10 +996,24 @@ extern "C" cmp_status cmp_rle_decompress(const uint8_t* const* in, const uint64_
   a.roi_out = roi_out_dev;
   a.status = status_dev;
   a.n = n;
+  a.at_roi = at_roi ? 1 : 0;
   const int64_t cap = resident_groups((const void*)rle_decompress_kernel, g_decompress_groups,
                                       g_decompress_cap.load(std::memory_order_relaxed));
   hipLaunchKernelGGL(rle_decompress_kernel, dim3((unsigned)(grid < cap ? grid : cap)),
                      dim3(kThreads), 0, (hipStream_t)stream, a);
   CMP_CHECK_HIP(hipGetLastError());
   return CMP_OK;
+}
+
+extern "C" cmp_status cmp_rle_decompress(const uint8_t* const* in, const uint64_t* in_bytes,
+                                         int32_t n, const cmp_image* out, int32_t* roi_out_dev,
+                                         int32_t* status_dev, void* stream) {
+  return rle_decompress_impl(in, in_bytes, n, out, roi_out_dev, status_dev, false, stream);
+}
+
+extern "C" cmp_status cmp_rle_decompress_at_roi(const uint8_t* const* in,
+                                                const uint64_t* in_bytes, int32_t n,
+                                                const cmp_image* out, int32_t* roi_out_dev,
+                                                int32_t* status_dev, void* stream) {
+  return rle_decompress_impl(in, in_bytes, n, out, roi_out_dev, status_dev, true, stream);
 }

@@ -352,6 +352,7 @@ struct RleDArgs {
   RleDImg im[kRleMax];
   int32_t* roi_out;
   int32_t* status;
+  int32_t at_roi;   // blocks go to their ROI's position in a frame (else to its top left)
   int32_t n;
 };
 static_assert(sizeof(RleDArgs) <= 4096, "kernel arguments must fit in 4 KiB");
