@@ -14,7 +14,8 @@ serve a step from the previous one.
 
 Prints one JSON line: Mpixel/s of composited input (the sum of the ROI areas
 supplied per frame) with frames composited asynchronously, four in flight
-on four streams with the RLE kernels at three workgroups per compute unit
+on four streams of the library's own with the RLE kernels at two
+workgroups per compute unit
 (one frame at a time, as a HIP graph and eagerly, at full occupancy, is
 reported beside it), the roofline of the dominant stage (algorithmic bytes
 over its event-timed average duration, one frame at a time), and the oracle
@@ -199,24 +200,24 @@ def time_stage_alone(frames, k, steps, warmup, s_obj):
 
 
 # Frames in flight in the headline run and the RLE kernels' workgroups per
-# compute unit there (measured with 12 buffer copies over 2, 3, 4 and 6
-# frames and caps 2, 3, 4 and all, us per step: 4 frames at 3 groups 116.5,
-# 4 at 2 116.9, 3 at 2 118.5, 3 at 3 120.0, 6 at 3 119.9, 2 at 3 119.5)
+# compute unit there, on streams created before any other (us per step with
+# 12 buffer copies, three processes each: 4 frames at 2 groups 110.0-111.1,
+# 4 at 3 111.5-112.4, 3 at 2 113.5-114.3, 3 at 3 114.2-116.4)
 PIPE_IN_FLIGHT = 4
-PIPE_RLE_GROUPS = 3
+PIPE_RLE_GROUPS = 2
 
 
-def time_pipelined(frames, steps, warmup, s_obj, in_flight=2):
+def time_pipelined(frames, steps, warmup, s_obj, streams):
     """Frames composited asynchronously (the thesis's pipelined compositing of
     consecutive frames, Section 5.4): step i runs the whole chain for buffer
-    copy i mod (copies) on stream i mod in_flight, so `in_flight` frames overlap
+    copy i mod (copies) on stream i mod len(streams), so that many frames overlap
     (a ROI scan or a compositing pass of one frame next to the RLE kernels
     of another). Each copy's steps stay in order on their stream. Returns
     the milliseconds and wall seconds of `steps` steps between a
     synchronize on each side."""
     nf = len(frames)
+    in_flight = len(streams)
     assert nf % in_flight == 0, "each buffer copy must stay on one stream"
-    streams = [torch.cuda.Stream() for _ in range(in_flight)]
 
     def run(count):
         for i in range(count):
@@ -565,6 +566,10 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    # the streams of the asynchronous run, made before any other stream: each
+    # then runs on a hardware queue of its own (cmp_streams_create)
+    in_flight = math.gcd(PIPE_IN_FLIGHT, args.copies)
+    pipe_streams = None if args.only else cmp.Streams(in_flight)
     if args.only in EXTRAS_ONLY:
         # profile helper for the extras: `steps` timed launches after two warm-up ones
         if args.only == "over_fp32":
@@ -637,15 +642,15 @@ def main():
                         "GBps": float(abytes[name] / alone_ms[k] / 1e6),
                         "us_in_chain": float(stage_ms[k] * 1e3)}
     dom = max(STAGES, key=lambda n: stages[n]["us"])
-    # several frames in flight: the RLE kernels leave a quarter of each
-    # compute unit to the other streams' kernels
-    in_flight = math.gcd(PIPE_IN_FLIGHT, len(frames))
+    # several frames in flight: the RLE kernels leave room on every compute
+    # unit to the other streams' kernels
     cmp.rle_set_groups_per_cu(PIPE_RLE_GROUPS, PIPE_RLE_GROUPS)
     try:
         pipe_total, pipe_wall = time_pipelined(frames, args.steps, args.warmup, s_obj,
-                                               in_flight=in_flight)
+                                               pipe_streams.streams)
     finally:
         cmp.rle_set_groups_per_cu(0, 0)
+        pipe_streams.close()
     pipe_ms = pipe_total / args.steps
     # one frame at a time as HIP graphs, after the asynchronous run: measured
     # before it, graph capture left the first asynchronous run ~15% slower

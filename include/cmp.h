@@ -458,6 +458,24 @@ cmp_status cmp_rle_decompress_at_roi(const uint8_t* const* in, const uint64_t* i
 cmp_status cmp_rle_set_groups_per_cu(int32_t compress, int32_t decompress);
 
 /*
+ * Streams for frames composited asynchronously (Section 5.4): writes
+ * `count` (1..16) new non-blocking streams of the default priority to
+ * streams[0..count) on the current device. The HIP runtime ties a stream to
+ * one of its hardware queues (GPU_MAX_HW_QUEUES of them, 4 by default) when
+ * the stream is created, and two busy streams on one queue run one after
+ * the other. Streams created before any stream but the null one ran side by
+ * side in every process measured; four taken from a framework's stream pool
+ * created later ran up to 14% slower in some processes and not in others.
+ * The caller owns the streams and releases them with cmp_streams_destroy
+ * (after their work). Errors: CMP_EINVAL (count out of range, NULL array),
+ * CMP_EHIP (creation failed: the streams created so far are destroyed and
+ * streams[] is left NULL).
+ */
+cmp_status cmp_streams_create(int32_t count, void** streams);
+/* Destroys count streams made by cmp_streams_create (NULL entries are skipped). */
+cmp_status cmp_streams_destroy(int32_t count, void* const* streams);
+
+/*
  * Test hook for the failure path of compression: the number of polls a
  * block makes for its predecessors' sizes before it gives up (negative:
  * the default of about a million). With a small limit, blocks whose

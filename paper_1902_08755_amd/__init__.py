@@ -104,6 +104,8 @@ def lib() -> ctypes.CDLL:
         "cmp_rle64_decompress": ([P, P, i32, IMG, P, P, P], i32),
         "cmp_rle_set_groups_per_cu": ([i32, i32], i32),
         "cmp_rle_set_wait_limit": ([i32], i32),
+        "cmp_streams_create": ([i32, ctypes.POINTER(P)], i32),
+        "cmp_streams_destroy": ([i32, ctypes.POINTER(P)], i32),
         "cmp_batch_plan_create": ([ctypes.POINTER(CJob), i32, ctypes.c_char_p,
                                    ctypes.POINTER(P)], i32),
         "cmp_batch_workspace_size": ([P], sz),
@@ -442,6 +444,25 @@ def rle_set_groups_per_cu(compress: int, decompress: int) -> None:
     """Cap the RLE kernels' workgroups per compute unit (cmp_rle_set_groups_per_cu);
     0 = as many as fit."""
     _check(lib().cmp_rle_set_groups_per_cu(compress, decompress), "cmp_rle_set_groups_per_cu")
+
+
+class Streams:
+    """``count`` streams of the library's own (cmp_streams_create), as
+    torch.cuda.ExternalStream objects in ``.streams``; destroyed by close()
+    after a device synchronisation. Create them before anything else makes a
+    stream for the hardware queue placement described in include/cmp.h."""
+
+    def __init__(self, count: int):
+        arr = (ctypes.c_void_p * count)()
+        _check(lib().cmp_streams_create(count, arr), "cmp_streams_create")
+        self._arr = arr
+        self.streams = [torch.cuda.ExternalStream(h) for h in arr]
+
+    def close(self):
+        if self._arr is not None:
+            torch.cuda.synchronize()
+            _check(lib().cmp_streams_destroy(len(self._arr), self._arr), "cmp_streams_destroy")
+            self._arr, self.streams = None, []
 
 
 def rle_decompress(streams: Sequence[torch.Tensor], outs: Sequence, stream=None, roi_out=None,

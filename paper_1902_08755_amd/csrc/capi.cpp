@@ -107,6 +107,32 @@ const char* cmp_status_string(cmp_status s) {
 
 const char* cmp_last_error(void) { return cmp::g_err; }
 
+cmp_status cmp_streams_create(int32_t count, void** streams) {
+  CMP_REQUIRE(streams && count >= 1 && count <= 16, "count %d: 1..16 streams", (int)count);
+  for (int i = 0; i < count; ++i) streams[i] = nullptr;
+  for (int i = 0; i < count; ++i) {
+    hipStream_t s = nullptr;
+    const hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      for (int j = 0; j < i; ++j) {
+        (void)hipStreamDestroy((hipStream_t)streams[j]);
+        streams[j] = nullptr;
+      }
+      return cmp::hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    streams[i] = s;
+  }
+  return CMP_OK;
+}
+
+cmp_status cmp_streams_destroy(int32_t count, void* const* streams) {
+  CMP_REQUIRE(count >= 0 && (count == 0 || streams), "count %d, streams %p", (int)count,
+              (const void*)streams);
+  for (int i = 0; i < count; ++i)
+    if (streams[i]) CMP_CHECK_HIP(hipStreamDestroy((hipStream_t)streams[i]));
+  return CMP_OK;
+}
+
 int32_t cmp_schedule_regions(cmp_schedule sched, cmp_rect viewport, cmp_rect* out, int32_t max) {
   if (viewport.w < 0 || viewport.h < 0 || max < 0 || (max > 0 && !out)) {
     cmp::set_error("invalid arguments");

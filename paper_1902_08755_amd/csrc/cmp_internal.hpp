@@ -60,6 +60,12 @@ __device__ __forceinline__ u32x4 ld_u32x4(const uint32_t* p) {
   __builtin_memcpy(&v, __builtin_assume_aligned(p, 4), 16);
   return v;
 }
+// A 16-byte global store marked non-temporal (streaming: the line is not
+// kept for reuse), at 4-byte alignment.
+typedef uint32_t u32x4u __attribute__((ext_vector_type(4), aligned(4)));
+__device__ __forceinline__ void st_u32x4_nt(uint32_t* p, u32x4 v) {
+  __builtin_nontemporal_store(u32x4u{v.x, v.y, v.z, v.w}, (__attribute__((address_space(1))) u32x4u*)p);
+}
 __device__ __forceinline__ void st_u32x4(uint32_t* p, u32x4 v) {
   __builtin_memcpy(__builtin_assume_aligned(p, 4), &v, 16);
 }

@@ -204,8 +204,8 @@ __device__ __forceinline__ void bwd_chunk(const BwdDesc* __restrict__ d, int j0,
     g.z = (float)(g2 * T);
     g.w = (float)(g3 * T - T * (double)e.y);
     // a global-address-space store cannot alias the kernel-argument copy
-    ((__attribute__((address_space(1))) f32x4*)(Dd.grad))
-        [(int64_t)(Y - Dd.y) * Dd.gpitch + (X - Dd.x)] = g;
+    __builtin_nontemporal_store(g, &((__attribute__((address_space(1))) f32x4*)(Dd.grad))
+        [(int64_t)(Y - Dd.y) * Dd.gpitch + (X - Dd.x)]);
     T = T * (1.0 - (double)e.x);
   }
 }

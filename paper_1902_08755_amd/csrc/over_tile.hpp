@@ -33,7 +33,9 @@ struct RawPx<CMP_RGBA16F> { typedef f16x4 type; };
 template <int FMT>
 __device__ __forceinline__ typename RawPx<FMT>::type ld_raw(const void* base, int64_t px) {
   typedef const __attribute__((address_space(1))) typename RawPx<FMT>::type* GPtr;
-  return ((GPtr)base)[px];
+  // non-temporal: each layer pixel is read once (measured faster than the
+  // default policy for this kernel and the backward pass)
+  return __builtin_nontemporal_load(&((GPtr)base)[px]);
 }
 __device__ __forceinline__ f32x4 widen(f32x4 v) { return v; }
 __device__ __forceinline__ f32x4 widen(f16x4 h) {
@@ -138,7 +140,7 @@ __device__ __forceinline__ void over_tile_seq(const OverDesc* __restrict__ d, in
     f32x4 acc = accumulate ? *o : f32x4{0.f, 0.f, 0.f, 0.f};
     acc = n <= 64 ? over_hits<FMT>(d, 0, hits, X, Y, acc)
                   : over_range<FMT>(d, 0, n, X, Y, x0, y0, tw, th, acc);
-    *o = acc;
+    __builtin_nontemporal_store(acc, o);
   }
 }
 
@@ -173,7 +175,7 @@ __device__ __forceinline__ void over_tile_tree(const OverDesc* __restrict__ d,
       lvl[l][threadIdx.x] = carry;
     }
     f32x4* o = reinterpret_cast<f32x4*>(out) + ((int64_t)(Y - vy) * out_pitch + (X - vx));
-    *o = lvl[levels][threadIdx.x];
+    __builtin_nontemporal_store(lvl[levels][threadIdx.x], o);
   }
 }
 

@@ -311,7 +311,8 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
       if (!poisoned) {
         u32x4* dst = reinterpret_cast<u32x4*>(out + P0 + excl);
         const u32x4* src = reinterpret_cast<const u32x4*>(stage);
-        for (uint32_t i = tid; i < padded / 16; i += kThreads) dst[i] = src[i];
+        for (uint32_t i = tid; i < padded / 16; i += kThreads)
+          __builtin_nontemporal_store(src[i], &dst[i]);   // streamed out, not re-read
       }
     }
   }
@@ -705,8 +706,8 @@ __global__ __launch_bounds__(kThreads, 4) void rle_decompress_kernel(const RleDA
       if (qq < len) {
         if (qq + 4 <= len && xx + 4 <= rw) {
           const int64_t o = (int64_t)yy * I.pitch + xx;
-          st_u32x4(ocol + o, cq[v]);
-          if (np == 8) st_u32x4(odep + o, dq[v]);
+          st_u32x4_nt(ocol + o, cq[v]);
+          if (np == 8) st_u32x4_nt(odep + o, dq[v]);
         } else {   // a quad at the end of a row or of the block
           int y2 = yy, x2 = xx;
 #pragma unroll

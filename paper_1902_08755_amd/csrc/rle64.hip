@@ -236,7 +236,8 @@ __global__ __launch_bounds__(kThreads, 4) void rle64_compress_kernel(const RleCA
     if (!poisoned) {
       u32x4* dst = reinterpret_cast<u32x4*>(out + P0 + excl);
       const u32x4* src = reinterpret_cast<const u32x4*>(stage);
-      for (uint32_t i = tid; i < padded / 16; i += kThreads) dst[i] = src[i];
+      for (uint32_t i = tid; i < padded / 16; i += kThreads)
+        __builtin_nontemporal_store(src[i], &dst[i]);   // streamed out, not re-read
     }
   }
   __syncthreads();   // the stage, the scan words and s_next are reused by the next slot

@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kThreads) void roi_kernel(const RoiArgs a) {
         ys[k] = y0 + ry;
         const u32x4* row =
             reinterpret_cast<const u32x4*>(base + (int64_t)(y0 + (ok ? ry : 0)) * row_bytes);
-        v[k] = row[ok ? u : 0];
+        v[k] = __builtin_nontemporal_load(&row[ok ? u : 0]);   // read once
         u += dr;
         ry += dq;
         if (u >= full_units) { u -= full_units; ++ry; }

@@ -225,3 +225,15 @@ def test_rle64_max_size_matches_oracle():
         for ns in (1, 2):
             assert L.cmp_rle64_max_size(w, h, ns) == oracle.rle64_max_size(w, h, ns), (w, h, ns)
     assert L.cmp_rle64_max_size(4, 4, 3) == 0 and L.cmp_rle64_max_size(-1, 4, 1) == 0
+
+
+def test_streams_create_rejects_bad_counts():
+    # checked before any HIP call
+    L = cmp.lib()
+    arr = (ctypes.c_void_p * 17)()
+    for count in (0, -1, 17):
+        assert L.cmp_streams_create(count, arr) == cmp.CMP_EINVAL
+    assert L.cmp_streams_create(2, None) == cmp.CMP_EINVAL
+    assert L.cmp_streams_destroy(-1, arr) == cmp.CMP_EINVAL
+    assert L.cmp_streams_destroy(1, None) == cmp.CMP_EINVAL
+    assert L.cmp_streams_destroy(0, None) == 0

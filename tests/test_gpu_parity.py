@@ -792,14 +792,16 @@ def test_ramp_pipeline_full_size():
     assert (ref_c == full_c).all() and (ref_d == full_d).all()
 
 
-@pytest.mark.parametrize("nframes,groups_per_cu", [(2, 0), (4, 3)])
-def test_frames_in_flight_match_one_at_a_time(nframes, groups_per_cu):
+@pytest.mark.parametrize("nframes,groups_per_cu,own_streams", [(2, 0, False), (4, 3, False),
+                                                              (4, 2, True)])
+def test_frames_in_flight_match_one_at_a_time(nframes, groups_per_cu, own_streams):
     """The benchmark's asynchronous mode: several frames' whole chains (ROI,
-    RLE compress, decompress, depth compositing) on as many streams at once,
-    with the RLE kernels' occupancy capped or not, give the same streams and
+    RLE compress, decompress, depth compositing) on as many streams at once
+    (torch's or the library's own, cmp_streams_create), with the RLE
+    kernels' occupancy capped or not, give the same streams and
     composites as running them one after the other (compressions on
     different streams overlap freely: blocks come from per-image tickets)."""
-    note(f"{nframes} frames in flight, RLE groups per CU {groups_per_cu}")
+    note(f"{nframes} frames in flight, RLE groups per CU {groups_per_cu}, own {own_streams}")
     frames = [synth.depth_ramps_full(seed=s, n=16, W=1920, H=1080, device=DEV)
               for s in range(2, 2 + nframes)]
 
@@ -824,8 +826,9 @@ def test_frames_in_flight_match_one_at_a_time(nframes, groups_per_cu):
     seq = [chain(wl, main) for wl in frames]
     torch.cuda.synchronize()
     cmp.rle_set_groups_per_cu(groups_per_cu, groups_per_cu)
+    own = cmp.Streams(nframes) if own_streams else None
     try:
-        side = [torch.cuda.Stream() for _ in frames]
+        side = own.streams if own else [torch.cuda.Stream() for _ in frames]
         for st in side:
             st.wait_stream(main)
         par = [chain(wl, st) for wl, st in zip(frames, side)]
@@ -834,6 +837,8 @@ def test_frames_in_flight_match_one_at_a_time(nframes, groups_per_cu):
         torch.cuda.synchronize()
     finally:
         cmp.rle_set_groups_per_cu(0, 0)
+        if own:
+            own.close()
     for a, b in zip(seq, par):
         assert torch.equal(a[0], b[0])
         assert (a[6] == 0).all() and (b[6] == 0).all()   # compression finished in time
