@@ -5,9 +5,11 @@ One step = the whole hot path over one frame of the 16-contributor workload
 region of interest with a smooth depth ramp plus noise):
     ROI detection of the 16 framebuffers
  -> per-component RLE compression of the 16 ROIs
- -> decompression of the 16 streams
- -> depth compositing of the 16 ROI blocks into 1920x1080 with the
-    binary-swap schedule over 16 owners (tiles of 480x270).
+ -> decompression of the 16 streams into 16 frames, each ROI block at its
+    position in the frame
+ -> depth compositing of the 16 frames cropped to the decoded ROIs into
+    1920x1080 with the binary-swap schedule over 16 owners (tiles of
+    480x270).
 Inputs are resident in HBM before timing starts; the step rotates over
 several copies of every buffer so that the 256 MB Infinity Cache cannot
 serve a step from the previous one.
@@ -56,7 +58,9 @@ class Frame:
         self.roi = torch.zeros((16, 4), dtype=torch.int32, device=dev)
         self.rle = cmp.RleBatch(self.images, roi_dev=self.roi)
         W, H = wl.viewport[2], wl.viewport[3]
-        self.blocks = [cmp.Image(torch.zeros((H, W), dtype=torch.int32, device=dev),
+        # the decoded frames: each ROI block lands at its position, and only
+        # the ROIs are read from them
+        self.placed = [cmp.Image(torch.zeros((H, W), dtype=torch.int32, device=dev),
                                  torch.zeros((H, W), dtype=torch.int32, device=dev), (0, 0, W, H))
                        for _ in self.images]
         self.roi_dec = torch.zeros((16, 4), dtype=torch.int32, device=dev)
@@ -71,8 +75,8 @@ class Frame:
                                   device=dev)
         self.dec_in = (ctypes.c_void_p * 16)(*[o.data_ptr() for o in self.rle.outs])
         self.dec_bytes = (ctypes.c_uint64 * 16)(*[o.numel() for o in self.rle.outs])
-        self.dec_out = cmp._images(self.blocks, "u32")
-        self.comp_in = cmp._images(self.blocks, "u32")
+        self.dec_out = cmp._images(self.placed, "u32")
+        self.comp_in = cmp._images(self.placed, "u32")
 
     def stage(self, k, s):
         L = cmp.lib()
@@ -85,13 +89,18 @@ class Frame:
                                     r.cap_arr, r.sizes.data_ptr(), r.status.data_ptr(),
                                     r.ws.data_ptr(), r.ws.numel(), s)
         elif k == 2:
-            st = L.cmp_rle_decompress(self.dec_in, self.dec_bytes, 16, self.dec_out,
-                                      self.roi_dec.data_ptr(), self.status.data_ptr(), s)
+            # each ROI block into its frame at the ROI's position: the
+            # compositor's 64-pixel row reads then start on the same column
+            # alignment as the viewport (blocks at the buffer origin made
+            # every wave's 256-byte read span three 128-byte lines: 1.40x
+            # the algorithmic bytes, against 1.09x)
+            st = L.cmp_rle_decompress_at_roi(self.dec_in, self.dec_bytes, 16, self.dec_out,
+                                             self.roi_dec.data_ptr(), self.status.data_ptr(), s)
         else:
-            st = L.cmp_composite_depth(self.comp_in, 16, self.roi_dec.data_ptr(),
-                                       cmp._rect(self.viewport), self.out_c.data_ptr(),
-                                       self.out_d.data_ptr(), self.out_c.stride(0),
-                                       cmp.Schedule(cmp.BINARY_SWAP, 16), cmp.Tile(0, 0), s)
+            st = L.cmp_composite_depth_crop(self.comp_in, 16, self.roi_dec.data_ptr(),
+                                            cmp._rect(self.viewport), self.out_c.data_ptr(),
+                                            self.out_d.data_ptr(), self.out_c.stride(0),
+                                            cmp.Schedule(cmp.BINARY_SWAP, 16), cmp.Tile(0, 0), s)
         if st != 0:
             raise cmp.CmpError(st, f"stage {k}", L.cmp_last_error().decode())
 
@@ -99,7 +108,7 @@ class Frame:
 STAGES = ["roi_detect", "rle_compress", "rle_decompress", "composite_depth"]
 # the kernels each stage launches (one library call per stage)
 STAGE_KERNELS = {"roi_detect": "roi_kernel<0>",
-                 "rle_compress": "rle_clear_kernel + rle_compress_kernel",
+                 "rle_compress": "rle_compress_kernel",
                  "rle_decompress": "rle_decompress_kernel",
                  "composite_depth": "depth_kernel"}
 

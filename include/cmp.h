@@ -337,9 +337,12 @@ size_t cmp_rle_max_size(int32_t w, int32_t h, int32_t nplanes);
  *                 unusable: the block's offset entry is set to 0xFFFFFFFF
  *                 (decompression rejects it with CMP_ECORRUPT), its payload is
  *                 not written, and out_size may be 0.
- *   workspace     device, >= cmp_rle_workspace_size(imgs, n) bytes; needs no
- *                 initialisation (each call clears what it uses). Calls
- *                 sharing a workspace must not overlap.
+ *   workspace     device, >= cmp_rle_workspace_size(imgs, n) bytes (per-image
+ *                 tickets, a call counter, a look-back flag per block),
+ *                 zero-filled before its first use; every call leaves it
+ *                 ready for the next (the last workgroup to finish zeroes
+ *                 the tickets; flags carry the call counter, so they are
+ *                 never cleared). Calls sharing a workspace must not overlap.
  * A block's payload offset is the sum of the sizes of the blocks before it
  * in its image, found on the device while the blocks are encoded (one
  * pass). Workgroups draw blocks from a ticket counter per image, in order,
@@ -364,14 +367,15 @@ cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_format fmt, ui
  * the first call on each device. The call allocates nothing.
  * Every call on a device shares that array: calls that overlap on one device
  * (on other streams, or graph replays running at the same time) race and
- * corrupt each other's streams; order them. Each call clears what it uses.
+ * corrupt each other's streams; order them. The array starts zeroed and
+ * every call leaves it ready for the next.
  * Limit: cmp_rle_workspace_size(imgs, n) <= CMP_RLE_SCRATCH_BYTES, i.e. at
  * most 131072 blocks of 4096 pixels over the n images (64 images of
  * 3840x2160 fit); beyond it CMP_ENOSPC and nothing is launched. Arguments,
  * results and other errors as cmp_rle_compress; CMP_EHIP if the array's
  * address cannot be found.
  */
-#define CMP_RLE_SCRATCH_BYTES ((size_t)8192 + (size_t)8 * 131072)
+#define CMP_RLE_SCRATCH_BYTES ((size_t)8192 + (size_t)256 + (size_t)8 * 131072)
 cmp_status cmp_rle_compress_noalloc(const cmp_image* imgs, int32_t n, cmp_format fmt,
                                     uint32_t flags, const int32_t* roi_dev, uint8_t* const* out,
                                     const uint64_t* capacity, uint64_t* out_size_dev,

@@ -21,8 +21,9 @@
 // (image, block) slots from a ticket counter per image (each on its own
 // cache line), so the blocks of an image go out in order and only to
 // running workgroups: every block a look-back waits for is held by a
-// workgroup that makes progress, whatever else runs on the device. A small
-// kernel clears the tickets and the look-back flags before each call.
+// workgroup that makes progress, whatever else runs on the device. No
+// kernel clears the workspace: the last workgroup to finish zeroes the
+// tickets, and the look-back flags carry a per-call epoch.
 // Every workgroup derives the slot count from the device ROIs, so blocks that
 // the ROIs leave out cost nothing.
 //
@@ -43,12 +44,6 @@
 #include "rle_common.hpp"
 
 namespace cmp {
-
-__global__ __launch_bounds__(kThreads) void rle_clear_kernel(uint64_t* p, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kThreads)
-    p[i] = 0;
-}
 
 // The tokens (run length - 1, value) of this lane's runs of one plane, from
 // token index idx on; 16-bit stores when the plane starts at an even offset.
@@ -88,6 +83,7 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
   __shared__ uint32_t t_slots[kRleMax];
   __shared__ int2 s_next;   // the slot drawn for the next iteration
   slot_table(a, t_roi, t_slots);
+  const uint32_t ep = call_epoch(a);
   __syncthreads();
 
   // Slots come from per-image tickets (draw_slot), drawn by wave 1: the
@@ -107,7 +103,10 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
   }
   __syncthreads();
   int2 cur = s_next;
-  if (cur.x < 0) return;   // uniform: nothing left for this workgroup
+  if (cur.x < 0) {   // uniform: nothing left for this workgroup
+    finish_call(a, ep);
+    return;
+  }
   uint32_t col[kPxPerLane], dep[kPxPerLane];
   CSlot nx = compress_slot(cur, t_roi);
   compress_load(a, nx, threadIdx.x, col, dep);
@@ -217,7 +216,7 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
       // prefix), so that successors need not wait for the staging below
       uint64_t* flags = a.flags + I.flag_base;
       if (tid == 0)
-        __hip_atomic_store(&flags[b], mkflag(b == 0 ? kIncl : kAgg, padded), __ATOMIC_RELAXED,
+        __hip_atomic_store(&flags[b], mkflag(b == 0 ? kIncl : kAgg, padded, ep), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
 
       // ---- stage the encoded block in LDS
@@ -267,7 +266,7 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
       // inclusive prefix, and moves the window back if it has none
       if (tid < kWave) {
         bool poisoned = false;
-        const uint32_t excl = lookback_excl(flags, b, padded, a.wait_limit, poisoned);
+        const uint32_t excl = lookback_excl(flags, b, padded, a.wait_limit, ep, poisoned);
         if (lane == 0) {
           s_excl = excl;
           s_poison = poisoned ? 1 : 0;
@@ -319,6 +318,7 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
   __syncthreads();   // the stage, the scan words and s_next are reused by the next slot
   if (!more) break;
   }
+  finish_call(a, ep);
 }
 
 // ---------------------------------------------------------- decompress
@@ -762,12 +762,6 @@ uint32_t rle_wait_limit() {
   return wl < 0 ? kDefaultWaitLimit : (uint32_t)wl;
 }
 int rle_compress_cap() { return g_compress_cap.load(std::memory_order_relaxed); }
-hipError_t launch_rle_clear(uint64_t* p, int64_t nwords, hipStream_t s) {
-  const int64_t grid = (nwords + kThreads - 1) / kThreads;
-  hipLaunchKernelGGL(rle_clear_kernel, dim3((unsigned)(grid < 1024 ? grid : 1024)), dim3(kThreads),
-                     0, s, p, nwords);
-  return hipGetLastError();
-}
 
 // Look-back flags: one per block of each image's largest possible ROI.
 int64_t rle_flag_count(const cmp_image* imgs, int32_t n) {
@@ -787,8 +781,8 @@ int64_t rle_flag_count(const cmp_image* imgs, int32_t n) {
 // name to a kernel (on the host it is only a stand-in for the symbol): it
 // passes the device address that hipGetSymbolAddress returns for the
 // current device, looked up once per device and kept in g_scratch_ptr.
-static_assert(CMP_RLE_SCRATCH_BYTES == kTicketBytes + 8 * 131072,
-              "the scratch holds the tickets and 131072 look-back flags");
+static_assert(CMP_RLE_SCRATCH_BYTES == kTicketBytes + kCtlBytes + 8 * 131072,
+              "the scratch holds the tickets, the control words and 131072 look-back flags");
 static __device__ __align__(256) uint8_t scratch[CMP_RLE_SCRATCH_BYTES];
 static std::mutex g_scratch_mu;
 static void* g_scratch_ptr[64];
@@ -830,7 +824,7 @@ extern "C" size_t cmp_rle_max_size(int32_t w, int32_t h, int32_t nplanes) {
 
 extern "C" size_t cmp_rle_workspace_size(const cmp_image* imgs, int32_t n) {
   if (n < 0 || (n > 0 && !imgs)) return 0;
-  return kTicketBytes + (size_t)(8 * rle_flag_count(imgs, n));
+  return kTicketBytes + kCtlBytes + (size_t)(8 * rle_flag_count(imgs, n));
 }
 
 namespace cmp {
@@ -839,7 +833,7 @@ cmp_status rle_compress_prepare(const cmp_image* imgs, int32_t n, const int32_t*
                                 uint8_t* const* out, const uint64_t* capacity,
                                 uint64_t* out_size_dev, int32_t* status_dev, void* workspace,
                                 size_t ws_bytes, size_t (*max_size)(int32_t, int32_t, bool),
-                                RleCArgs& a, int64_t& grid, hipStream_t stream) {
+                                RleCArgs& a, int64_t& grid) {
   CMP_REQUIRE(imgs && out && capacity && out_size_dev && status_dev && workspace, "NULL argument");
   CMP_REQUIRE(((uintptr_t)roi_dev & 15) == 0 && ((uintptr_t)workspace & 15) == 0 &&
                   ((uintptr_t)out_size_dev & 7) == 0 && ((uintptr_t)status_dev & 3) == 0,
@@ -871,7 +865,7 @@ cmp_status rle_compress_prepare(const cmp_image* imgs, int32_t n, const int32_t*
     grid += nb ? nb : 1;
   }
   CMP_REQUIRE(grid < (1ll << 24), "too many blocks");
-  const size_t need = kTicketBytes + (size_t)(8 * nflags);
+  const size_t need = kTicketBytes + kCtlBytes + (size_t)(8 * nflags);
   if (ws_bytes < need) {
     set_error("workspace of %zu bytes is smaller than %zu", ws_bytes, need);
     return CMP_ENOSPC;
@@ -880,17 +874,10 @@ cmp_status rle_compress_prepare(const cmp_image* imgs, int32_t n, const int32_t*
   a.out_size = out_size_dev;
   a.status = status_dev;
   a.tickets = (uint32_t*)workspace;
-  a.flags = (uint64_t*)((uint8_t*)workspace + kTicketBytes);
+  a.ctl = (uint32_t*)((uint8_t*)workspace + kTicketBytes);
+  a.flags = (uint64_t*)((uint8_t*)workspace + kTicketBytes + kCtlBytes);
   a.n = n;
   a.wait_limit = rle_wait_limit();
-  // the tickets and the look-back flags are cleared by a kernel, so that
-  // graph replays clear them too
-  const hipError_t e = launch_rle_clear((uint64_t*)workspace, (int64_t)(kTicketBytes / 8) + nflags,
-                                        stream);
-  if (e != hipSuccess) {
-    set_error("HIP error %d (%s) launching the clear kernel", (int)e, hipGetErrorString(e));
-    return CMP_EHIP;
-  }
   return CMP_OK;
 }
 
@@ -917,7 +904,7 @@ extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_for
   hipStream_t s = (hipStream_t)stream;
   const cmp_status st = rle_compress_prepare(imgs, n, roi_dev, out, capacity, out_size_dev,
                                              status_dev, workspace, ws_bytes, rle1_max_size, a,
-                                             grid, s);
+                                             grid);
   if (st != CMP_OK) return st;
   a.swizzle = (flags & CMP_RLE_SWIZZLE) ? 1 : 0;
   // one wave of workgroups at most: more would find the tickets drawn

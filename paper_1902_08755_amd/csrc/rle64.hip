@@ -57,6 +57,7 @@ __global__ __launch_bounds__(kThreads, 4) void rle64_compress_kernel(const RleCA
   __shared__ uint32_t t_slots[kRleMax];
   __shared__ int2 s_next;   // the slot drawn for the next iteration
   slot_table(a, t_roi, t_slots);
+  const uint32_t ep = call_epoch(a);
   __syncthreads();
 
   // Slots as in the per-component compressor: per-image tickets drawn by
@@ -68,7 +69,10 @@ __global__ __launch_bounds__(kThreads, 4) void rle64_compress_kernel(const RleCA
   }
   __syncthreads();
   int2 cur = s_next;
-  if (cur.x < 0) return;   // uniform: nothing left for this workgroup
+  if (cur.x < 0) {   // uniform: nothing left for this workgroup
+    finish_call(a, ep);
+    return;
+  }
   uint32_t col[kPxPerLane], dep[kPxPerLane];
   CSlot nx = compress_slot(cur, t_roi);
   compress_load(a, nx, threadIdx.x, col, dep);
@@ -157,7 +161,7 @@ __global__ __launch_bounds__(kThreads, 4) void rle64_compress_kernel(const RleCA
     const uint32_t padded = (uint32_t)align16(total);
     uint64_t* flags = a.flags + I.flag_base;
     if (tid == 0)
-      __hip_atomic_store(&flags[b], mkflag(b == 0 ? kIncl : kAgg, padded), __ATOMIC_RELAXED,
+      __hip_atomic_store(&flags[b], mkflag(b == 0 ? kIncl : kAgg, padded, ep), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
 
     // ---- stage the encoded block in LDS
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(kThreads, 4) void rle64_compress_kernel(const RleCA
     // ---- payload offset (wave 0); the next slot's pixels go in flight
     if (tid < kWave) {
       bool poisoned = false;
-      const uint32_t excl = lookback_excl(flags, b, padded, a.wait_limit, poisoned);
+      const uint32_t excl = lookback_excl(flags, b, padded, a.wait_limit, ep, poisoned);
       if (lane == 0) {
         s_excl = excl;
         s_poison = poisoned ? 1 : 0;
@@ -243,6 +247,7 @@ __global__ __launch_bounds__(kThreads, 4) void rle64_compress_kernel(const RleCA
   __syncthreads();   // the stage, the scan words and s_next are reused by the next slot
   if (!more) break;
   }
+  finish_call(a, ep);
 }
 
 // ---------------------------------------------------------- decompress
@@ -566,7 +571,7 @@ extern "C" cmp_status cmp_rle64_compress(const cmp_image* imgs, int32_t n, cmp_f
   hipStream_t s = (hipStream_t)stream;
   const cmp_status st = rle_compress_prepare(imgs, n, roi_dev, out, capacity, out_size_dev,
                                              status_dev, workspace, ws_bytes, rl64_max_size_of, a,
-                                             grid, s);
+                                             grid);
   if (st != CMP_OK) return st;
   const int64_t cap = resident_groups((const void*)rle64_compress_kernel,
                                       g_rl64_compress_groups, rle_compress_cap());

@@ -139,6 +139,7 @@ struct RleCArgs {
   uint64_t* out_size;
   int32_t* status;
   uint32_t* tickets;       // workspace: a ticket counter per image, kTicketStride words apart
+  uint32_t* ctl;           // workspace: the call epoch (word 0), finished workgroups (word kCtlDone)
   uint64_t* flags;         // workspace: one flag per (image, block)
   int32_t n;
   int32_t swizzle;         // CMP_RLE_SWIZZLE
@@ -147,17 +148,65 @@ struct RleCArgs {
 static_assert(sizeof(RleCArgs) <= 4096, "kernel arguments must fit in 4 KiB");
 
 // Workspace: the ticket counters (one per image, each on its own 128-byte
-// line), then the look-back flags; rle_clear_kernel zeroes both before
-// every compression.
+// line), two control words (the call epoch and a count of finished
+// workgroups, on lines of their own), then the look-back flags. It is
+// zero-filled once, before its first use; every call leaves it ready for the
+// next: the last workgroup to finish zeroes the tickets and the count and
+// advances the epoch, and a flag written by an earlier call (another epoch)
+// reads as not ready, so the flags are never cleared.
 constexpr int kTicketStride = 32;
 constexpr size_t kTicketBytes = (size_t)kRleMax * kTicketStride * 4;
+constexpr int kCtlDone = 32;   // word index of the finished-workgroup count
+constexpr size_t kCtlBytes = 256;
+constexpr uint32_t kEpochMask = (1u << 30) - 1;
 
-// look-back flag: status (2 bits) << 32 | value (32 bits); 0 = not ready.
-// kPoison marks a block whose offset is unknown (a bounded wait gave up):
-// neither it nor any later block of the image writes its payload.
+// look-back flag: epoch (30 bits) << 34 | status (2 bits) << 32 | value (32
+// bits); status 0, or another call's epoch, = not ready. kPoison marks a
+// block whose offset is unknown (a bounded wait gave up): neither it nor
+// any later block of the image writes its payload.
 constexpr uint64_t kAgg = 1, kIncl = 2, kPoison = 3;
 constexpr int kLookback = 4;   // flags per lane per look-back step
-__device__ __forceinline__ uint64_t mkflag(uint64_t st, uint32_t v) { return (st << 32) | v; }
+__device__ __forceinline__ uint64_t mkflag(uint64_t st, uint32_t v, uint32_t ep) {
+  return ((uint64_t)ep << 34) | (st << 32) | v;
+}
+__device__ __forceinline__ uint64_t flag_state(uint64_t f, uint32_t ep) {
+  return (uint32_t)(f >> 34) == ep ? (f >> 32) & 3u : 0u;
+}
+
+// The epoch of this call (every workgroup reads it at its start; only the
+// previous call's last workgroup wrote it). Loaded into a vector register
+// and first used at the block's flag, so that the load's latency passes
+// while the pixels arrive (made uniform there, it held up the first ticket
+// draw).
+__device__ __forceinline__ uint32_t call_epoch(const RleCArgs& a) {
+  return __hip_atomic_load(a.ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kEpochMask;
+}
+
+// Every workgroup ends here, after its last use of the tickets and flags:
+// the last one to arrive zeroes the tickets of this call's images and the
+// count, and advances the epoch, ready for the next call on the workspace.
+// Relaxed atomics suffice: every ticket access is a device-scope atomic, and
+// a workgroup's last draw has returned before its count is added; the next
+// call reads the epoch after this kernel has ended. (An acquire-release
+// count, which writes back the L2 at each workgroup's exit, made a 16 x
+// 1920x1080 compression 40% slower.)
+__device__ __forceinline__ void finish_call(const RleCArgs& a, uint32_t ep) {
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    s_last = __hip_atomic_fetch_add(a.ctl + kCtlDone, 1u, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+  __syncthreads();
+  if (s_last) {
+    for (int i = threadIdx.x; i < a.n; i += kThreads)
+      __hip_atomic_store(a.tickets + i * kTicketStride, 0u, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(a.ctl + kCtlDone, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(a.ctl, (ep + 1) & kEpochMask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
 
 
 // Byte k of each of four words, gathered into one word: one column of a
@@ -417,7 +466,8 @@ __device__ __forceinline__ void slot_table(const RleCArgs& a, int4* t_roi, uint3
 // published by the caller). A wait that runs out of polls, or a poisoned
 // prefix, sets `poisoned` and poisons b's flag instead.
 __device__ __forceinline__ uint32_t lookback_excl(uint64_t* flags, int b, uint32_t padded,
-                                                  uint32_t wait_limit, bool& poisoned) {
+                                                  uint32_t wait_limit, uint32_t ep,
+                                                  bool& poisoned) {
   const int lane = threadIdx.x % kWave;
   uint32_t excl = 0;
   poisoned = false;
@@ -429,7 +479,7 @@ __device__ __forceinline__ uint32_t lookback_excl(uint64_t* flags, int b, uint32
 #pragma unroll
     for (int i = 0; i < kLookback; ++i) {
       const int p = top - (kWave * i + lane);
-      f[i] = mkflag(kIncl, 0);   // before block 0: an empty prefix
+      f[i] = mkflag(kIncl, 0, ep);   // before block 0: an empty prefix
       if (p >= 0) f[i] = __hip_atomic_load(&flags[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     // the nearest inclusive (or poisoned) prefix, at distance 64 i + lane,
@@ -438,14 +488,14 @@ __device__ __forceinline__ uint32_t lookback_excl(uint64_t* flags, int b, uint32
     bool waiting = false;
 #pragma unroll
     for (int i = kLookback - 1; i >= 0; --i) {
-      const uint64_t st = (f[i] >> 32) & 3u;
+      const uint64_t st = flag_state(f[i], ep);
       const uint64_t incl = __ballot(st >= kIncl);
       if (incl) first = kWave * i + (int)__builtin_ctzll(incl);
     }
     uint64_t pz = 0;
 #pragma unroll
     for (int i = 0; i < kLookback; ++i) {
-      const uint64_t st = (f[i] >> 32) & 3u;
+      const uint64_t st = flag_state(f[i], ep);
       if (__ballot(st == 0 && kWave * i + lane <= first)) waiting = true;
       pz |= __ballot(st == kPoison && kWave * i + lane == first);
     }
@@ -472,7 +522,8 @@ __device__ __forceinline__ uint32_t lookback_excl(uint64_t* flags, int b, uint32
     top -= kWave * kLookback;
   }
   if (lane == 0)
-    __hip_atomic_store(&flags[b], poisoned ? mkflag(kPoison, 0) : mkflag(kIncl, excl + padded),
+    __hip_atomic_store(&flags[b],
+                       poisoned ? mkflag(kPoison, 0, ep) : mkflag(kIncl, excl + padded, ep),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return excl;
 }
@@ -488,16 +539,13 @@ int64_t rle_flag_count(const cmp_image* imgs, int32_t n);
 uint32_t rle_wait_limit();
 // Caps on the compressors' workgroups per compute unit (0: as many as fit).
 int rle_compress_cap();
-// Enqueues the kernel that zeroes `nwords` 64-bit words (tickets and flags).
-hipError_t launch_rle_clear(uint64_t* p, int64_t nwords, hipStream_t s);
 // Validates a compression call of n images whose streams need at most
-// max_size(w, h, has depth) bytes, fills `a` (all but the codec's flags) and
-// `grid` (the number of slots), and enqueues the clearing of the tickets
-// and look-back flags. Nothing is enqueued on an error.
+// max_size(w, h, has depth) bytes and fills `a` (all but the codec's flags)
+// and `grid` (the number of slots). Enqueues nothing.
 cmp_status rle_compress_prepare(const cmp_image* imgs, int32_t n, const int32_t* roi_dev,
                                 uint8_t* const* out, const uint64_t* capacity,
                                 uint64_t* out_size_dev, int32_t* status_dev, void* workspace,
                                 size_t ws_bytes, size_t (*max_size)(int32_t, int32_t, bool),
-                                RleCArgs& a, int64_t& grid, hipStream_t stream);
+                                RleCArgs& a, int64_t& grid);
 
 }  // namespace cmp
