@@ -671,22 +671,29 @@ __global__ __launch_bounds__(kThreads, 4) void rle_decompress_kernel(const RleDA
   {
     const int wave = tid / kWave;
     uint8_t* wbase = vals + (kBlock / 4) * wave;
-    // lane L's colour at piece L / 16, bytes 64 (L % 16) ..; depth 4 pieces on
-    uint8_t* wl = wbase + (lane / 16) * kBlock + (lane % 16) * 64;
+    // quad q of the wave (pixels 4 q ..) sits in piece q / 64 at slot
+    // swz(q % 64): within each group of 8 slots (128 bytes, all banks) the
+    // slots rotate by the group index, so that the 8 lanes served together
+    // hit 8 different 16-byte bank groups both when lane L writes its quads
+    // 4 L + c and when lane i reads quad 64 v + i
+    auto swz = [](int x) { return (x & ~7) | ((x + (x >> 3)) & 7); };
+    uint8_t* wl = wbase + (lane / 16) * kBlock;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      *reinterpret_cast<u32x4*>(wl + 16 * c) =
+      const int slot = 16 * swz((4 * lane + c) % 64);
+      *reinterpret_cast<u32x4*>(wl + slot) =
           u32x4{col[4 * c], col[4 * c + 1], col[4 * c + 2], col[4 * c + 3]};
       if (np == 8)
-        *reinterpret_cast<u32x4*>(wl + 4 * kBlock + 16 * c) =
+        *reinterpret_cast<u32x4*>(wl + 4 * kBlock + slot) =
             u32x4{dep[4 * c], dep[4 * c + 1], dep[4 * c + 2], dep[4 * c + 3]};
     }
     __builtin_amdgcn_wave_barrier();
     u32x4 cq[4], dq[4];
+    const int rslot = 16 * swz(lane);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      cq[v] = *reinterpret_cast<const u32x4*>(wbase + v * kBlock + 16 * lane);
-      dq[v] = np == 8 ? *reinterpret_cast<const u32x4*>(wbase + (4 + v) * kBlock + 16 * lane)
+      cq[v] = *reinterpret_cast<const u32x4*>(wbase + v * kBlock + rslot);
+      dq[v] = np == 8 ? *reinterpret_cast<const u32x4*>(wbase + (4 + v) * kBlock + rslot)
                       : u32x4{0, 0, 0, 0};
     }
     // the block's first pixel (uniform), then the quad's by a 32-bit division
