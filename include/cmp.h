@@ -29,6 +29,13 @@
  *  - A contributor's `roi` places its w x h block of pixels at (roi.x, roi.y)
  *    in destination pixel space (Section 5.3, Region of Interest: the ROI is
  *    sent with the pixels and used to place them on the input frame).
+ *
+ * Environment (read by the library, never required):
+ *  - CMP_LOG=1: each plan (schedule regions and tiles, ROI, RLE and batch
+ *    launch geometry, the tune cache a batch plan used) is written to stderr
+ *    as one "[cmp] ..." line. Read once per process.
+ *  - CMP_TUNE_CACHE=<path>: the tune cache that cmp_batch_plan_create and
+ *    cmp_autotune use when their path argument is NULL.
  */
 #ifndef CMP_H
 #define CMP_H
@@ -510,8 +517,9 @@ typedef struct {
 
 typedef struct cmp_batch_plan cmp_batch_plan;
 
-/* Builds the work list on the host. tune_cache_path: NULL, or a text file
- * written by cmp_autotune whose tile choices are used. */
+/* Builds the work list on the host. tune_cache_path: a text file written by
+ * cmp_autotune whose tile choices are used, or NULL: the file named by
+ * CMP_TUNE_CACHE, if set, else the default tiles. */
 cmp_status cmp_batch_plan_create(const cmp_job* jobs, int32_t njobs, const char* tune_cache_path,
                                  cmp_batch_plan** plan);
 size_t     cmp_batch_workspace_size(const cmp_batch_plan* plan);
@@ -531,8 +539,9 @@ void       cmp_batch_plan_destroy(cmp_batch_plan* plan);
  * Autotuner: for every (kind, format, contributor-count bucket, size bucket)
  * that occurs in `jobs`, times each candidate tile with plain launches of a
  * representative job on `stream` (synchronising it) and writes the fastest
- * tile per bucket to the text file `cache_path`. Results never depend on the
- * tile. Writes only the jobs' outputs.
+ * tile per bucket to the text file `cache_path` (NULL: the file named by
+ * CMP_TUNE_CACHE; CMP_EINVAL if that is unset too). Results never depend on
+ * the tile. Writes only the jobs' outputs.
  */
 cmp_status cmp_autotune(const cmp_job* jobs, int32_t njobs, const char* cache_path, int32_t reps,
                         void* stream);

@@ -19,6 +19,7 @@
 // size bucket) with plain launches and stores the winners in a text cache.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -257,6 +258,8 @@ extern "C" cmp_status cmp_batch_plan_create(const cmp_job* jobs, int32_t njobs,
     if (st != CMP_OK) return st;
   }
   cmp_batch_plan* P = new cmp_batch_plan();
+  // no path given: the cache named by CMP_TUNE_CACHE, if any
+  if (!tune_cache_path) tune_cache_path = getenv("CMP_TUNE_CACHE");
   const std::vector<TuneEntry> cache = read_cache(tune_cache_path);
   std::vector<JobRec> recs;
   std::vector<DepthDesc> dd;
@@ -356,6 +359,9 @@ extern "C" cmp_status cmp_batch_plan_create(const cmp_job* jobs, int32_t njobs,
     return CMP_EHIP;
   }
   P->grid = std::max(1, cus * std::max(1, per_cu));
+  log_plan("batch plan: %d jobs, %d work items, %d resident workgroups, tune cache %s (%zu "
+           "entries for this device)", njobs, P->nitems, P->grid,
+           tune_cache_path ? tune_cache_path : "none", cache.size());
   *plan = P;
   return CMP_OK;
 }
@@ -415,7 +421,9 @@ extern "C" void cmp_batch_plan_destroy(cmp_batch_plan* plan) { delete plan; }
 
 extern "C" cmp_status cmp_autotune(const cmp_job* jobs, int32_t njobs, const char* cache_path,
                                    int32_t reps, void* stream) {
-  CMP_REQUIRE(njobs >= 0 && (njobs == 0 || jobs) && cache_path, "bad arguments");
+  if (!cache_path) cache_path = getenv("CMP_TUNE_CACHE");
+  CMP_REQUIRE(njobs >= 0 && (njobs == 0 || jobs) && cache_path,
+              "bad arguments (no cache path given and CMP_TUNE_CACHE unset)");
   CMP_REQUIRE(reps >= 1, "reps must be >= 1");
   for (int i = 0; i < njobs; ++i) {
     cmp_status st = validate_job(jobs[i], i);

@@ -2,6 +2,10 @@
 // text and the schedule planner shared by the compositing entry points.
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <atomic>
 
 #include "cmp_internal.hpp"
 
@@ -19,6 +23,28 @@ void set_error(const char* fmt, ...) {
 cmp_status hip_fail(hipError_t e, const char* what) {
   set_error("%s: %s", what, hipGetErrorString(e));
   return CMP_EHIP;
+}
+
+static std::atomic<int> g_log{-1};   // -1: CMP_LOG not read yet
+
+bool log_enabled() {
+  int v = g_log.load(std::memory_order_relaxed);
+  if (v < 0) {
+    const char* e = getenv("CMP_LOG");
+    v = (e && *e && strcmp(e, "0") != 0) ? 1 : 0;
+    g_log.store(v, std::memory_order_relaxed);
+  }
+  return v == 1;
+}
+
+void log_plan(const char* fmt, ...) {
+  if (!log_enabled()) return;
+  char line[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(line, sizeof line, fmt, ap);
+  va_end(ap);
+  fprintf(stderr, "[cmp] %s\n", line);
 }
 
 static void push_region(Region* out, int& nreg, int64_t& tiles, int x, int y, int w, int h,
@@ -83,6 +109,9 @@ int plan_regions(cmp_schedule sched, cmp_rect vp, int tw, int th, Region* out,
       return CMP_EINVAL;
   }
   *total_tiles = tiles;
+  log_plan("schedule kind %d (%d owners) over %dx%d at (%d,%d): %d regions, tiles %dx%d, %lld "
+           "workgroups", (int)sched.kind, (int)sched.owners, vp.w, vp.h, vp.x, vp.y, nreg, tw, th,
+           (long long)tiles);
   return nreg;
 }
 

@@ -17,6 +17,10 @@ constexpr int kWave = 64;
 // ----------------------------------------------------------------- host
 void set_error(const char* fmt, ...);
 cmp_status hip_fail(hipError_t e, const char* what);
+// Plan logging: with CMP_LOG=1 in the environment (read once per process),
+// log_plan writes one "[cmp] ..." line to stderr; otherwise it does nothing.
+bool log_enabled();
+void log_plan(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
 
 #define CMP_CHECK_HIP(expr)                                  \
   do {                                                       \

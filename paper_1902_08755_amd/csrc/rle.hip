@@ -919,6 +919,8 @@ extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_for
   const int64_t cap = resident_groups((const void*)rle_compress_kernel<false>, g_compress_groups,
                                       rle_compress_cap());
   const dim3 grid_dim((unsigned)(grid < cap ? grid : cap));
+  log_plan("rle compress: %d images, %lld block slots, %u resident workgroups%s", n,
+           (long long)grid, grid_dim.x, a.swizzle ? ", swizzled" : "");
   if (a.swizzle)
     hipLaunchKernelGGL(rle_compress_kernel<true>, grid_dim, dim3(kThreads), 0, s, a);
   else
@@ -994,6 +996,8 @@ static cmp_status rle_decompress_impl(const uint8_t* const* in, const uint64_t* 
   a.at_roi = at_roi ? 1 : 0;
   const int64_t cap = resident_groups((const void*)rle_decompress_kernel, g_decompress_groups,
                                       g_decompress_cap.load(std::memory_order_relaxed));
+  log_plan("rle decompress: %d streams, at most %lld blocks, %lld resident workgroups%s", n,
+           (long long)grid, (long long)(grid < cap ? grid : cap), at_roi ? ", at the ROIs" : "");
   hipLaunchKernelGGL(rle_decompress_kernel, dim3((unsigned)(grid < cap ? grid : cap)),
                      dim3(kThreads), 0, (hipStream_t)stream, a);
   CMP_CHECK_HIP(hipGetLastError());

@@ -389,6 +389,7 @@ extern "C" cmp_status cmp_roi_detect(const cmp_image* imgs, int32_t n, cmp_forma
   a.n = n;
   a.mode = mode;
   hipStream_t s = (hipStream_t)stream;
+  log_plan("roi detect: %d images, format mode %d, %lld workgroups", n, mode, (long long)wg);
   switch (mode) {
     case 0: hipLaunchKernelGGL(roi_kernel<0>, dim3((unsigned)wg), dim3(kThreads), 0, s, a); break;
     case 1: hipLaunchKernelGGL(roi_kernel<1>, dim3((unsigned)wg), dim3(kThreads), 0, s, a); break;

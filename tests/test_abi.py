@@ -11,6 +11,8 @@ import pytest
 import oracle
 import paper_1902_08755_amd as cmp
 
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
 HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "cmp.h")
 
 
@@ -237,3 +239,37 @@ def test_streams_create_rejects_bad_counts():
     assert L.cmp_streams_destroy(-1, arr) == cmp.CMP_EINVAL
     assert L.cmp_streams_destroy(1, None) == cmp.CMP_EINVAL
     assert L.cmp_streams_destroy(0, None) == 0
+
+
+def test_cmp_log_writes_plans_to_stderr():
+    # CMP_LOG=1: a schedule plan (host-only call) is written to stderr as one
+    # "[cmp] ..." line; without it nothing is written
+    import subprocess
+    import sys
+    code = ("import paper_1902_08755_amd as cmp; L = cmp.lib(); "
+            "out = (cmp.Rect * 64)(); "
+            "n = L.cmp_schedule_regions(cmp.Schedule(cmp.BINARY_SWAP, 16), cmp.Rect(0, 0, 1920, 1080), out, 64); "
+            "assert n == 16, n")
+    env = dict(os.environ, CMP_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    lines = [l for l in r.stderr.splitlines() if l.startswith("[cmp] ")]
+    assert len(lines) == 1 and "16 regions" in lines[0] and "1920x1080" in lines[0], r.stderr
+    env.pop("CMP_LOG")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 0 and "[cmp]" not in r.stderr, r.stderr
+
+
+def test_autotune_without_cache_path_or_env_is_rejected():
+    # no path and CMP_TUNE_CACHE unset: rejected on the host, nothing runs
+    L = cmp.lib()
+    saved = os.environ.pop("CMP_TUNE_CACHE", None)
+    try:
+        job = cmp.CJob()
+        assert L.cmp_autotune(ctypes.byref(job), 1, None, 1, None) == cmp.CMP_EINVAL
+        assert "CMP_TUNE_CACHE" in L.cmp_last_error().decode()
+    finally:
+        if saved is not None:
+            os.environ["CMP_TUNE_CACHE"] = saved

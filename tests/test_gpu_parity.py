@@ -7,6 +7,8 @@ for bit; float work within the stated tolerances:
 """
 import sys
 
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -718,6 +720,40 @@ def test_batch_tune_cache_tiles_do_not_change_results(tmp_path):
     for p in (plan_d, plan_t, plan_l):
         L.cmp_batch_plan_destroy(p)
     del keep_d, keep_t, keep_l
+
+
+def test_batch_plan_reads_tune_cache_from_environment(tmp_path):
+    """cmp_batch_plan_create with no path uses the tune cache named by
+    CMP_TUNE_CACHE: in a child process with CMP_LOG=1, the plan's log line
+    names that file and the entries it read for this device."""
+    import subprocess
+    import sys
+    jobs = synth.batch_jobs(seed=9, njobs=6, device=DEV, log2_range=(5.0, 7.0))
+    L = cmp.lib()
+    s = torch.cuda.current_stream().cuda_stream
+    cache = str(tmp_path / "tune.txt")
+    outs = _alloc_outs(jobs)
+    arr, keep = _cjobs(jobs, outs)
+    note("batch tune cache from CMP_TUNE_CACHE")
+    assert L.cmp_autotune(arr, len(jobs), cache.encode(), 1, s) == 0, L.cmp_last_error()
+    torch.cuda.synchronize()
+    code = (
+        "import ctypes, paper_1902_08755_amd as cmp\n"
+        "L = cmp.lib()\n"
+        "img = (cmp.CImage * 1)(cmp.CImage(0x10000, 0x20000, 64, cmp.Rect(0, 0, 64, 64)))\n"
+        "job = cmp.CJob(0, cmp.RGBA8, 1, img, None, cmp.Rect(0, 0, 64, 64), 0x30000, 0x40000, 64)\n"
+        "plan = ctypes.c_void_p()\n"
+        "assert L.cmp_batch_plan_create(ctypes.byref(job), 1, None, ctypes.byref(plan)) == 0\n"
+        "L.cmp_batch_plan_destroy(plan)\n")
+    env = dict(os.environ, CMP_LOG="1", CMP_TUNE_CACHE=cache)
+    r = subprocess.run([sys.executable, "-c", code], cwd=os.path.dirname(os.path.dirname(
+        os.path.abspath(__file__))), env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [ln for ln in r.stderr.splitlines() if ln.startswith("[cmp] batch plan")]
+    assert len(lines) == 1 and f"tune cache {cache} (" in lines[0], r.stderr[-2000:]
+    entries = int(lines[0].split(f"tune cache {cache} (")[1].split()[0])
+    assert entries > 0, lines[0]
+    del keep
 
 
 def test_batch_graph_replay():
