@@ -16,9 +16,8 @@ serve a step from the previous one.
 
 Prints one JSON line: Mpixel/s of composited input (the sum of the ROI areas
 supplied per frame) with frames composited asynchronously, four in flight
-on four streams of the library's own with the RLE kernels at two
-workgroups per compute unit
-(one frame at a time, as a HIP graph and eagerly, at full occupancy, is
+on four streams of the library's own, compression capped at one workgroup
+and decompression at three per compute unit (one frame at a time, as a HIP graph and eagerly, at full occupancy, is
 reported beside it), the roofline of the dominant stage (algorithmic bytes
 over its event-timed average duration, one frame at a time), and the oracle
 timed on the host.
@@ -210,10 +209,13 @@ def time_stage_alone(frames, k, steps, warmup, s_obj):
 
 # Frames in flight in the headline run and the RLE kernels' workgroups per
 # compute unit there, on streams created before any other (us per step with
-# 12 buffer copies, three processes each: 4 frames at 2 groups 110.0-111.1,
-# 4 at 3 111.5-112.4, 3 at 2 113.5-114.3, 3 at 3 114.2-116.4)
+# 12 buffer copies: 4 frames with both RLE kernels at 2 groups 110.0-111.1,
+# both at 3 111.5-112.4, 3 frames at 2 113.5-114.3; with 4 frames, compress x
+# decompress caps 1x3 106.1-106.5, 1x2 106.5-106.9, 1x4 106.3-106.8, 1x1
+# 106.9-108.9, 2x3 108.4-108.6, 2x2 109.0-109.7, 3x2 111.3-111.9, 4x2 113.3-113.5)
 PIPE_IN_FLIGHT = 4
-PIPE_RLE_GROUPS = 2
+PIPE_COMPRESS_GROUPS = 1
+PIPE_DECOMPRESS_GROUPS = 3
 
 
 def time_pipelined(frames, steps, warmup, s_obj, streams):
@@ -653,7 +655,7 @@ def main():
     dom = max(STAGES, key=lambda n: stages[n]["us"])
     # several frames in flight: the RLE kernels leave room on every compute
     # unit to the other streams' kernels
-    cmp.rle_set_groups_per_cu(PIPE_RLE_GROUPS, PIPE_RLE_GROUPS)
+    cmp.rle_set_groups_per_cu(PIPE_COMPRESS_GROUPS, PIPE_DECOMPRESS_GROUPS)
     try:
         pipe_total, pipe_wall = time_pipelined(frames, args.steps, args.warmup, s_obj,
                                                pipe_streams.streams)
@@ -695,14 +697,16 @@ def main():
                    "roi_area_fraction": "0.25-0.35", "schedule": "binary_swap(16)",
                    "composited_input_px_per_step": roi_px, "buffer_copies": args.copies},
         "timing": f"value and ms_per_step: frames composited asynchronously, {in_flight} in "
-                  f"flight (each frame's whole chain on one of {in_flight} streams, RLE kernels "
-                  f"at {PIPE_RLE_GROUPS} workgroups per CU); graph: one frame at a time, its five "
+                  f"flight (each frame's whole chain on one of {in_flight} streams, compression at "
+                  f"{PIPE_COMPRESS_GROUPS} and decompression at {PIPE_DECOMPRESS_GROUPS} "
+                  "workgroups per CU); graph: one frame at a time, its four "
                   "launches replayed as a HIP graph; eager: the chain one frame at a time; stages "
                   "and roofline: each stage launched back to back over the buffer copies between two "
                   "events (us_in_chain: between per-stage events inside the eager chain), RLE "
                   "kernels at full occupancy",
         "frames_in_flight": in_flight,
-        "pipelined_rle_groups_per_cu": PIPE_RLE_GROUPS,
+        "pipelined_rle_groups_per_cu": {"compress": PIPE_COMPRESS_GROUPS,
+                                        "decompress": PIPE_DECOMPRESS_GROUPS},
         "graph_ms_per_step": graph_ms,
         "eager_ms_per_step": ms_step,
         "hbm_GBps_step": step_bytes / pipe_ms / 1e6,
