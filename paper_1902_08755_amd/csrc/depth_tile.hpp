@@ -91,8 +91,10 @@ __device__ __forceinline__ void stage_contributors(const DepthSrc& src, int n, D
 }
 
 // `rec`: contributors staged by stage_contributors (n <= kPlaceMax).
-// Per step a wave first finds, from LDS, which contributors cover its rows
-// and the tile's columns (a 64-bit mask), then loads kDepthBatch covering
+// Per step a wave first finds which contributors cover its rows and the
+// tile's columns: lane i tests contributor i and one ballot gives the 64-bit
+// mask (a loop over the contributors with uniform compares took a quarter of
+// the kernel's vector instructions). It then loads kDepthBatch covering
 // contributors x 4 rows at a time, so the depth loads of a typical step are
 // one round trip; the winner's colour is gathered at the end.
 __device__ __forceinline__ void depth_tile(const DepthRec* rec, int n, int x0, int y0, int tw,
@@ -108,15 +110,16 @@ __device__ __forceinline__ void depth_tile(const DepthRec* rec, int n, int x0, i
     for (int r0 = wave * kDepthRows; r0 < th; r0 += kStepRows) {
       const int Y0 = y0 + r0;                       // rows Y0 .. Y0 + 3 (uniform)
       const int nrows = min(kDepthRows, th - r0);
-      // covering contributors of this step (uniform)
-      uint64_t cover = 0;
-      for (int i = 0; i < n; ++i) {
-        const int rx = uniform(rec[i].x), ry = uniform(rec[i].y);
-        const int rw = uniform(rec[i].w), rh = uniform(rec[i].h);
-        if (rw > 0 && rx < cx1 && rx + rw > cx0 && ry < Y0 + nrows && ry + rh > Y0)
-          cover |= 1ull << i;
+      // covering contributors of this step: lane i tests contributor i
+      // (n <= 64), one ballot gives the mask (bit i: contributor i). Every
+      // lane of the wave is active here: the loops above are uniform over
+      // the wave and callers run depth_tile with the whole workgroup.
+      bool covers_i = false;
+      if (lane < n) {
+        const DepthRec& R = rec[lane];
+        covers_i = R.w > 0 && R.x < cx1 && R.x + R.w > cx0 && R.y < Y0 + nrows && R.y + R.h > Y0;
       }
-      cover = (uint64_t)uniform64((int64_t)cover);
+      uint64_t cover = (uint64_t)__ballot(covers_i);
       uint32_t bd[kDepthRows], pc[kDepthRows];
       int bi[kDepthRows];
 #pragma unroll
@@ -148,22 +151,26 @@ __device__ __forceinline__ void depth_tile(const DepthRec* rec, int n, int x0, i
 #pragma unroll
         for (int j = 0; j < kDepthBatch; ++j) {
           const int i = ids[j];
-          const int rx = uniform(rec[i].x), ry = uniform(rec[i].y);
-          const int rw = uniform(rec[i].w), rh = uniform(rec[i].h);
+          // the column test is per lane anyway: x and w stay in vector registers
+          const int rx = rec[i].x, ry = uniform(rec[i].y);
+          const int rw = rec[i].w, rh = uniform(rec[i].h);
           // global (not flat) loads: flat ones would also hold up the LDS counter
           const GlobalU32 dep = (GlobalU32)uniform_ptr(rec[i].depth);
           const int64_t pitch = uniform64(rec[i].pitch);
           const bool in_col = has[j] && col_ok && X >= rx && X < rx + rw;
           const int lo = in_col ? X - rx : 0;   // this lane's column in the contributor
-          // a uniform row address plus the lane's column; a pixel outside
-          // the contributor reads the first pixel of a valid row instead
+          // a uniform row offset (one multiply per contributor, then one
+          // pitch per row) plus the lane's column; a pixel outside the
+          // contributor reads the first pixel of a valid row instead
+          const int yy0 = Y0 - ry;               // uniform
+          int64_t roff = (int64_t)yy0 * pitch;
 #pragma unroll
           for (int k = 0; k < kDepthRows; ++k) {
-            const int yy = Y0 + k - ry;           // uniform
+            const int yy = yy0 + k;
             const bool rok = k < nrows && yy >= 0 && yy < rh;
-            const GlobalU32 row = rok ? dep + (int64_t)yy * pitch : dep;
-            dv[j][k] = row[lo];
+            dv[j][k] = dep[(rok ? roff : 0) + lo];
             ok[j][k] = rok && in_col;
+            roff += pitch;
           }
         }
         // ascending indices and a strict "<": ties keep the lower index
