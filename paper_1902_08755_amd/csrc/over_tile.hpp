@@ -81,6 +81,20 @@ __device__ __forceinline__ uint64_t tile_hits(const OverDesc* __restrict__ d, in
   return (uint64_t)uniform64((int64_t)m);
 }
 
+// tile_hits by one ballot: lane i tests layer c0 + i (c1 - c0 <= 64). Every
+// lane of the wave must be active (a lane outside the wave's work casts no
+// vote): callers take it before their per-pixel loops.
+__device__ __forceinline__ uint64_t tile_hits_wave(const OverDesc* __restrict__ d, int c0, int c1,
+                                                   int x0, int y0, int tw, int th) {
+  const int j = c0 + (int)(threadIdx.x % kWave);
+  bool hit = false;
+  if (j < c1) {
+    const OverDesc& D = d[j];
+    hit = !tile_misses(D.x, D.y, D.w, D.h, x0, y0, tw, th);
+  }
+  return (uint64_t)__ballot(hit);
+}
+
 // Blends, in increasing order, the layers base + i for the set bits i of
 // `hits` (layers that reach the tile) at pixel (X, Y) onto acc. A batch's
 // loads are unconditional, so that no branch separates them: a slot past
@@ -131,7 +145,7 @@ __device__ __forceinline__ void over_tile_seq(const OverDesc* __restrict__ d, in
                                               bool accumulate) {
   const int np = tw * th;
   // the layers that reach the tile, found once for all its pixels (n <= 64)
-  const uint64_t hits = n <= 64 ? tile_hits(d, 0, n, x0, y0, tw, th) : 0;
+  const uint64_t hits = n <= 64 ? tile_hits_wave(d, 0, n, x0, y0, tw, th) : 0;
   for (int p = threadIdx.x; p < np; p += kThreads) {
     const int r = p / tw;
     const int c = p - r * tw;
@@ -161,7 +175,7 @@ __device__ __forceinline__ void over_tile_tree(const OverDesc* __restrict__ d,
   int levels = 0;
   while ((1 << levels) < groups) ++levels;
   // n <= 64 layers in all (one pass): the tile's layers found once
-  const uint64_t hits = tile_hits(d, 0, gb[groups], x0, y0, tw, th);
+  const uint64_t hits = tile_hits_wave(d, 0, gb[groups], x0, y0, tw, th);
   for (int p = threadIdx.x; p < np; p += kThreads) {
     const int r = p / tw;
     const int c = p - r * tw;
