@@ -76,6 +76,7 @@ constexpr int kChunk = 32;
 constexpr int kBwdInline = 64;                        // descriptors in the kernel arguments
 constexpr int kBwdMaxLayers = 256;                    // with a descriptor workspace
 constexpr int kBwdCkpt = kBwdMaxLayers / kChunk - 1;  // checkpoints of the general kernel
+constexpr int kBwdMaxChunks = kBwdMaxLayers / kChunk;
 
 struct BwdDesc {
   const void* color;
@@ -98,19 +99,6 @@ static_assert(sizeof(BwdArgs) <= 4096, "kernel arguments must fit in 4 KiB");
 
 __device__ __forceinline__ bool covers(const BwdDesc& D, int X, int Y) {
   return X >= D.x && X < D.x + D.w && Y >= D.y && Y < D.y + D.h;
-}
-
-// Positions [j0, j1) (j1 - j0 <= 32) whose layers reach the tile, as a mask
-// (bit i: position j0 + i). Uniform.
-__device__ __forceinline__ uint32_t bwd_hits(const BwdDesc* __restrict__ d, int j0, int j1, int x0,
-                                             int y0, int tw, int th) {
-  uint32_t m = 0;
-  for (int j = j0; j < j1; ++j) {
-    const BwdDesc& D = d[j];
-    if (!tile_misses(uniform(D.x), uniform(D.y), uniform(D.w), uniform(D.h), x0, y0, tw, th))
-      m |= 1u << (j - j0);
-  }
-  return (uint32_t)uniform((int)m);
 }
 
 template <int FMT>
@@ -217,12 +205,30 @@ template <int FMT, bool kInline>
 __global__ __launch_bounds__(kThreads) void over_bwd_kernel(const BwdArgs a) {
   __shared__ float2 st[kChunk][kThreads];
   __shared__ double tck[kInline ? 1 : kBwdCkpt][kThreads];
+  __shared__ uint32_t s_hits[kBwdMaxChunks];
   const BwdDesc* d = kInline ? a.c : a.desc;
   const int ty = blockIdx.x / a.tiles_x, tx = blockIdx.x - ty * a.tiles_x;
   const int x0 = a.vx + tx * a.tile_w, y0 = a.vy + ty * a.tile_h;
   const int tw = min(a.tile_w, a.vx + a.vw - x0), th = min(a.tile_h, a.vy + a.vh - y0);
   const int np = tw * th;
   const int n = a.n, nch = (n + kChunk - 1) / kChunk;
+  // each chunk's layer mask for this tile, found once, before the per-pixel
+  // loop (every lane active): wave w takes chunks w, w + 4, ...; lane i
+  // tests position i of the chunk and one ballot gives the mask
+  {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    for (int ch = wave; ch < nch; ch += kThreads / kWave) {
+      const int j = ch * kChunk + lane;
+      bool hit = false;
+      if (lane < kChunk && j < n) {
+        const BwdDesc& D = d[j];
+        hit = !tile_misses(D.x, D.y, D.w, D.h, x0, y0, tw, th);
+      }
+      const uint32_t m = (uint32_t)__ballot(hit);
+      if (lane == 0) s_hits[ch] = m;
+    }
+  }
+  __syncthreads();
   for (int p = threadIdx.x; p < np; p += kThreads) {
     const int r = p / tw;
     const int c = p - r * tw;
@@ -234,17 +240,17 @@ __global__ __launch_bounds__(kThreads) void over_bwd_kernel(const BwdArgs a) {
     {
       double T = 1.0;
       for (int ch = nch - 1; ch >= 1; --ch) {
-        const int j0 = ch * kChunk, j1 = min(n, j0 + kChunk);
-        T = bwd_alpha_product<FMT>(d, j0, bwd_hits(d, j0, j1, x0, y0, tw, th), X, Y, T);
+        const int j0 = ch * kChunk;
+        T = bwd_alpha_product<FMT>(d, j0, s_hits[ch], X, Y, T);
         if (kInline) T1 = T;
         else tck[ch - 1][threadIdx.x] = T;
       }
     }
     double S[4] = {0.0, 0.0, 0.0, 0.0};
     for (int ch = 0; ch < nch; ++ch) {
-      const int j0 = ch * kChunk, j1 = min(n, j0 + kChunk);
+      const int j0 = ch * kChunk;
       const double T = ch == nch - 1 ? 1.0 : kInline ? T1 : tck[ch][threadIdx.x];
-      bwd_chunk<FMT>(d, j0, bwd_hits(d, j0, j1, x0, y0, tw, th), X, Y, G, S, T, st);
+      bwd_chunk<FMT>(d, j0, s_hits[ch], X, Y, G, S, T, st);
     }
   }
 }
