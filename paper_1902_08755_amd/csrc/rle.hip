@@ -264,21 +264,24 @@ __global__ __launch_bounds__(kThreads, 4) void rle_compress_kernel(const RleCArg
       // flags of 256 predecessors at once (4 per lane, each load instruction
       // contiguous over the lanes), sums the aggregates up to the nearest
       // inclusive prefix, and moves the window back if it has none
+      bool lb_poison = false;
+      uint32_t lb_excl = 0;
       if (tid < kWave) {
-        bool poisoned = false;
-        const uint32_t excl = lookback_excl(flags, b, padded, a.wait_limit, ep, poisoned);
+        lb_excl = lookback_excl(flags, b, padded, a.wait_limit, ep, lb_poison);
         if (lane == 0) {
-          s_excl = excl;
-          s_poison = poisoned ? 1 : 0;
-          if (poisoned) a.status[s] = CMP_ETIMEOUT;
+          s_excl = lb_excl;
+          s_poison = lb_poison ? 1 : 0;
+          if (lb_poison) a.status[s] = CMP_ETIMEOUT;
         }
       }
       // the next slot's pixels go in flight: waves 1..3 during the look-back,
-      // wave 0 after it (its flag loads must not wait behind these loads)
+      // wave 0 after it (its flag loads must not wait behind these loads),
+      // then wave 0 publishes the block's inclusive prefix
       if (more) {
         nx = compress_slot(cur, t_roi);
         compress_load(a, nx, tid, col, dep);
       }
+      if (tid < kWave) publish_incl(flags, b, lb_excl, padded, lb_poison, ep);
       __syncthreads();
       const uint32_t excl = s_excl;
       const bool poisoned = s_poison != 0;

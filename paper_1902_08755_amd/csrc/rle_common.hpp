@@ -462,9 +462,11 @@ __device__ __forceinline__ void slot_table(const RleCArgs& a, int4* t_roi, uint3
 // run by all 64 lanes of one wave: the sum of the payload sizes of blocks
 // 0..b-1, read from their flags 256 at a time (4 per lane, each load
 // instruction contiguous over the lanes), summing aggregates back to the
-// nearest inclusive prefix. Publishes b's inclusive flag (b's aggregate was
-// published by the caller). A wait that runs out of polls, or a poisoned
-// prefix, sets `poisoned` and poisons b's flag instead.
+// nearest inclusive prefix. A wait that runs out of polls, or a poisoned
+// prefix, sets `poisoned`. The caller publishes b's inclusive (or poisoned)
+// flag with publish_incl once its own next loads are issued: a wave that
+// still has that store in flight waits for its completion at its next full
+// memory wait, which the loads' issue would otherwise sit behind.
 __device__ __forceinline__ uint32_t lookback_excl(uint64_t* flags, int b, uint32_t padded,
                                                   uint32_t wait_limit, uint32_t ep,
                                                   bool& poisoned) {
@@ -521,11 +523,18 @@ __device__ __forceinline__ uint32_t lookback_excl(uint64_t* flags, int b, uint32
     if (first < kWave * kLookback) break;
     top -= kWave * kLookback;
   }
-  if (lane == 0)
+  return excl;
+}
+
+// Block b's inclusive prefix (excl + padded), or its poisoned flag; lane 0
+// of the wave that ran lookback_excl. Block 0 published its inclusive
+// prefix with its size.
+__device__ __forceinline__ void publish_incl(uint64_t* flags, int b, uint32_t excl,
+                                             uint32_t padded, bool poisoned, uint32_t ep) {
+  if (b != 0 && threadIdx.x % kWave == 0)
     __hip_atomic_store(&flags[b],
                        poisoned ? mkflag(kPoison, 0, ep) : mkflag(kIncl, excl + padded, ep),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return excl;
 }
 
 // ---------------------------------------------------------------- host
