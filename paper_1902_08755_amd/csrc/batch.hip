@@ -57,7 +57,11 @@ struct BatchArgs {
   int32_t nitems;
 };
 
-__global__ __launch_bounds__(kThreads) void batch_kernel(const BatchArgs a) {
+// Built for at least six waves per SIMD: at the compiler's default the
+// kernel took 84 VGPRs (five waves); asked for six it fits in 72 with no
+// spill and runs at seven (256 jobs: 1.947 -> 1.895 ms). Eight spills.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void batch_kernel(
+    const BatchArgs a) {
   __shared__ int s_item;
   __shared__ DepthRec s_rec[kPlaceMax];   // contributors of the current depth job
   __shared__ OverDesc s_od[kOverStage];   // layers of the current over job

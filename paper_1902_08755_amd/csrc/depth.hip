@@ -44,7 +44,7 @@ __device__ __forceinline__ void tile_of_block(const Region* reg, int nreg, int t
 // Eight waves per SIMD: at the compiler's default the kernel used 106 SGPRs,
 // which held it to seven (measured on 16 x 1920x1080 cropped frames:
 // 22.85 -> 21.7 us; forcing eight on the over and batch kernels made them
-// spill and run slower, so they keep the default).
+// spill and run slower).
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void depth_kernel(
     const DepthArgs a) {
   int x0, y0, tw, th;
