@@ -183,13 +183,19 @@ __global__ __launch_bounds__(kThreads, 4) void rle64_compress_kernel(const RleCA
         const int next_after = row_shl_fill<1>(fs, seg_end);
         uint32_t idx = (ex[0] >> (16 * k)) & 0xFFFFu;
         const uint32_t vals = off + align8u(runs[k]);
-        while (mm) {
-          const int i = __builtin_ctz(mm);
-          mm &= mm - 1u;
-          const int end = mm ? j0 + __builtin_ctz(mm) : next_after;
-          stage[off + idx] = (uint8_t)(end - j0 - i - 1);
-          *reinterpret_cast<uint2*>(stage + vals + 8 * idx) = uint2{w[2 * i], w[2 * i + 1]};
-          ++idx;
+        // one unrolled step per symbol slot, so that the symbol registers are
+        // indexed by constants: indexed by the run's position instead, they
+        // went to scratch memory (144 bytes per lane, 2.3x the kernel's HBM
+        // bytes)
+#pragma unroll
+        for (int i = 0; i < kSymLane; ++i) {
+          if (mm & (1u << i)) {
+            const uint32_t later = mm & ~((2u << i) - 1u);   // starts after symbol i
+            const int end = later ? j0 + __builtin_ctz(later) : next_after;
+            stage[off + idx] = (uint8_t)(end - j0 - i - 1);
+            *reinterpret_cast<uint2*>(stage + vals + 8 * idx) = uint2{w[2 * i], w[2 * i + 1]};
+            ++idx;
+          }
         }
         if (tid < (int)(align8u(runs[k]) - runs[k])) stage[off + runs[k] + tid] = 0;
       } else {
