@@ -348,8 +348,9 @@ size_t cmp_rle_max_size(int32_t w, int32_t h, int32_t nplanes);
  *                 tickets, a call counter, a look-back flag per block),
  *                 zero-filled before its first use; every call leaves it
  *                 ready for the next (the last workgroup to finish zeroes
- *                 the tickets; flags carry the call counter, so they are
- *                 never cleared). Calls sharing a workspace must not overlap.
+ *                 the tickets; flags carry the 30-bit call counter, so they
+ *                 are cleared only by the call that wraps it, once in 2^30
+ *                 calls). Calls sharing a workspace must not overlap.
  * A block's payload offset is the sum of the sizes of the blocks before it
  * in its image, found on the device while the blocks are encoded (one
  * pass). Workgroups draw blocks from a ticket counter per image, in order,

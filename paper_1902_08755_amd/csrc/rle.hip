@@ -886,6 +886,7 @@ cmp_status rle_compress_prepare(const cmp_image* imgs, int32_t n, const int32_t*
   a.tickets = (uint32_t*)workspace;
   a.ctl = (uint32_t*)((uint8_t*)workspace + kTicketBytes);
   a.flags = (uint64_t*)((uint8_t*)workspace + kTicketBytes + kCtlBytes);
+  a.nflags = (int32_t)nflags;
   a.n = n;
   a.wait_limit = rle_wait_limit();
   return CMP_OK;

@@ -139,8 +139,10 @@ struct RleCArgs {
   uint64_t* out_size;
   int32_t* status;
   uint32_t* tickets;       // workspace: a ticket counter per image, kTicketStride words apart
-  uint32_t* ctl;           // workspace: the call epoch (word 0), finished workgroups (word kCtlDone)
+  uint32_t* ctl;           // workspace: the call epoch (word 0), finished workgroups (word
+                           // kCtlDone), the most flags any call has used (word kCtlHwm)
   uint64_t* flags;         // workspace: one flag per (image, block)
+  int32_t nflags;          // flags of this call
   int32_t n;
   int32_t swizzle;         // CMP_RLE_SWIZZLE
   uint32_t wait_limit;     // look-back polls before a block gives up
@@ -148,15 +150,19 @@ struct RleCArgs {
 static_assert(sizeof(RleCArgs) <= 4096, "kernel arguments must fit in 4 KiB");
 
 // Workspace: the ticket counters (one per image, each on its own 128-byte
-// line), two control words (the call epoch and a count of finished
-// workgroups, on lines of their own), then the look-back flags. It is
-// zero-filled once, before its first use; every call leaves it ready for the
-// next: the last workgroup to finish zeroes the tickets and the count and
-// advances the epoch, and a flag written by an earlier call (another epoch)
-// reads as not ready, so the flags are never cleared.
+// line), control words (the call epoch on one line; the count of finished
+// workgroups and the most flags any call has used on another), then the
+// look-back flags. It is zero-filled once, before its first use; every call
+// leaves it ready for the next: the last workgroup to finish zeroes the
+// tickets and the count and advances the epoch, and a flag written by an
+// earlier call (another epoch) reads as not ready, so the flags are not
+// cleared, except when the 30-bit epoch wraps to 0: then the flags that
+// calls have used so far are zeroed, since those of the calls 2^30 earlier
+// would read as current again.
 constexpr int kTicketStride = 32;
 constexpr size_t kTicketBytes = (size_t)kRleMax * kTicketStride * 4;
 constexpr int kCtlDone = 32;   // word index of the finished-workgroup count
+constexpr int kCtlHwm = 33;    // word index of the most flags any call has used
 constexpr size_t kCtlBytes = 256;
 constexpr uint32_t kEpochMask = (1u << 30) - 1;
 
@@ -184,7 +190,9 @@ __device__ __forceinline__ uint32_t call_epoch(const RleCArgs& a) {
 
 // Every workgroup ends here, after its last use of the tickets and flags:
 // the last one to arrive zeroes the tickets of this call's images and the
-// count, and advances the epoch, ready for the next call on the workspace.
+// count, raises the flag high-water mark to this call's flags, and advances
+// the epoch, ready for the next call on the workspace; if the epoch wraps to
+// 0 it first zeroes the flags below the high-water mark.
 // Relaxed atomics suffice: every ticket access is a device-scope atomic, and
 // a workgroup's last draw has returned before its count is added; the next
 // call reads the epoch after this kernel has ended. (An acquire-release
@@ -201,9 +209,19 @@ __device__ __forceinline__ void finish_call(const RleCArgs& a, uint32_t ep) {
     for (int i = threadIdx.x; i < a.n; i += kThreads)
       __hip_atomic_store(a.tickets + i * kTicketStride, 0u, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t hwm =
+        max(__hip_atomic_load(a.ctl + kCtlHwm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+            (uint32_t)a.nflags);
+    const uint32_t next = (ep + 1) & kEpochMask;
+    if (next == 0) {
+      for (uint32_t i = threadIdx.x; i < hwm; i += kThreads)
+        __hip_atomic_store(a.flags + i, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();   // every thread has read the high-water mark
     if (threadIdx.x == 0) {
+      __hip_atomic_store(a.ctl + kCtlHwm, hwm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(a.ctl + kCtlDone, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(a.ctl, (ep + 1) & kEpochMask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(a.ctl, next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }

@@ -210,6 +210,61 @@ def _check_streams(imgs, rois, streams, sizes):
         assert (streams[k][:n].cpu().numpy() == ref).all(), k
 
 
+def _run_images(rng, n, H, W, max_run):
+    """n images of H x W (colour and depth) made of runs of 1..max_run pixels."""
+    imgs = []
+    for _ in range(n):
+        planes = []
+        for _ in range(2):
+            lens = rng.integers(1, max_run + 1, H * W)
+            vals = rng.integers(0, 2 ** 32, H * W, dtype=np.uint64).astype(np.uint32)
+            planes.append(np.repeat(vals, lens)[:H * W].reshape(H, W))
+        imgs.append(cmp.Image(torch.from_numpy(planes[0].view(np.int32)).to(DEV),
+                              torch.from_numpy(planes[1].view(np.int32)).to(DEV), (0, 0, W, H)))
+    return imgs
+
+
+def test_rle_call_counter_wrap_clears_flags():
+    """The compression workspace's 30-bit call counter wraps after 2^30 calls.
+    Forced from the host (the counter word set to 2^30 - 1), the wrapping call
+    zeroes the look-back flags of every earlier call, so that the next call,
+    which runs under counter 0 as the workspace's first call did, cannot take
+    a flag of that first call (same layout, other sizes) for its own."""
+    rng = np.random.default_rng(11)
+    a = _run_images(rng, 4, 480, 640, 12)     # the first call: 4 x 75 blocks
+    a2 = _run_images(rng, 4, 480, 640, 3)     # same block layout, other stream sizes
+    c = _run_images(rng, 1, 64, 64, 5)        # the wrapping call: one block
+    ba, ba2, bc = cmp.RleBatch(a), cmp.RleBatch(a2), cmp.RleBatch(c)
+    ws = ba.ws
+    ba2.ws = bc.ws = ws
+    ctl = 8192 // 4                           # word index of the counter (after the tickets)
+    hwm_word, flags0, nflags = ctl + 33, 8192 + 256, 4 * 75
+    words = ws.view(torch.int32)
+    note("rle call counter wrap: first call")
+    streams, sizes, _ = ba.run()
+    torch.cuda.synchronize()
+    assert int(ba.status.abs().sum()) == 0
+    assert int(words[ctl]) == 1 and int(words[hwm_word]) == nflags
+    _check_streams(a, [im.roi for im in a], streams, sizes)
+    flags = ws[flags0:flags0 + 8 * nflags].view(torch.int64)
+    assert int((flags != 0).sum()) == nflags   # every block published a flag under counter 0
+    words[ctl] = (1 << 30) - 1
+    note("rle call counter wrap: the wrapping call")
+    streams, sizes, _ = bc.run()
+    torch.cuda.synchronize()
+    assert int(bc.status.abs().sum()) == 0
+    _check_streams(c, [im.roi for im in c], streams, sizes)
+    assert int(words[ctl]) == 0 and int(words[hwm_word]) == nflags
+    assert int((ws[flags0:flags0 + 8 * nflags] != 0).sum()) == 0
+    note("rle call counter wrap: the call after it, under counter 0 again")
+    for rep in range(2):
+        streams, sizes, _ = ba2.run()
+        torch.cuda.synchronize()
+        assert int(ba2.status.abs().sum()) == 0
+        _check_streams(a2, [im.roi for im in a2], streams, sizes)
+    assert int(words[ctl]) == 2
+
+
 def test_rle_rect_composite_round_trip():
     """RLE of the composite of the 640x480 rectangle workload, ROI from the GPU."""
     wl = synth.depth_rects(seed=1, n=4, W=640, H=480, device=DEV)
