@@ -376,6 +376,7 @@ extern "C" size_t cmp_batch_workspace_size(const cmp_batch_plan* plan) {
 
 extern "C" cmp_status cmp_batch_upload(const cmp_batch_plan* plan, void* workspace,
                                        size_t ws_bytes, void* stream) {
+  CMP_RANGE("cmp_batch_upload");
   CMP_REQUIRE(plan && workspace, "NULL argument");
   CMP_REQUIRE(((uintptr_t)workspace & 63) == 0, "workspace must be 64-byte aligned");
   if (ws_bytes < plan->blob.size()) {
@@ -388,6 +389,7 @@ extern "C" cmp_status cmp_batch_upload(const cmp_batch_plan* plan, void* workspa
 }
 
 extern "C" cmp_status cmp_batch_run(const cmp_batch_plan* plan, void* workspace, void* stream) {
+  CMP_RANGE("cmp_batch_run");
   CMP_REQUIRE(plan && workspace, "NULL argument");
   if (plan->nitems == 0) return CMP_OK;
   char* w = (char*)workspace;
@@ -405,6 +407,7 @@ extern "C" cmp_status cmp_batch_run(const cmp_batch_plan* plan, void* workspace,
 }
 
 extern "C" cmp_status cmp_batch_run_plain(const cmp_batch_plan* plan, void* stream) {
+  CMP_RANGE("cmp_batch_run_plain");
   CMP_REQUIRE(plan, "NULL plan");
   for (size_t i = 0; i < plan->jobs.size(); ++i) {
     const cmp_status st = plain_job(plan->jobs[i], plan->tiles[i], (hipStream_t)stream);
@@ -425,6 +428,7 @@ extern "C" void cmp_batch_plan_destroy(cmp_batch_plan* plan) { delete plan; }
 
 extern "C" cmp_status cmp_autotune(const cmp_job* jobs, int32_t njobs, const char* cache_path,
                                    int32_t reps, void* stream) {
+  CMP_RANGE("cmp_autotune");
   if (!cache_path) cache_path = getenv("CMP_TUNE_CACHE");
   CMP_REQUIRE(njobs >= 0 && (njobs == 0 || jobs) && cache_path,
               "bad arguments (no cache path given and CMP_TUNE_CACHE unset)");

@@ -1,11 +1,13 @@
 // Host-side helpers of libcmp: version, status strings, the per-thread error
 // text and the schedule planner shared by the compositing entry points.
+#include <dlfcn.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include <atomic>
+#include <mutex>
 
 #include "cmp_internal.hpp"
 
@@ -45,6 +47,44 @@ void log_plan(const char* fmt, ...) {
   vsnprintf(line, sizeof line, fmt, ap);
   va_end(ap);
   fprintf(stderr, "[cmp] %s\n", line);
+}
+
+// roctx, resolved on first use when CMP_ROCTX is set: -1 not looked up yet,
+// 0 off (unset, or the library is missing), 1 on.
+typedef int (*roctx_push_fn)(const char*);
+typedef int (*roctx_pop_fn)();
+static std::atomic<int> g_roctx{-1};
+static roctx_push_fn g_roctx_push = nullptr;
+static roctx_pop_fn g_roctx_pop = nullptr;
+
+static bool roctx_on() {
+  int v = g_roctx.load(std::memory_order_acquire);
+  if (v >= 0) return v == 1;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  v = g_roctx.load(std::memory_order_relaxed);
+  if (v >= 0) return v == 1;
+  v = 0;
+  const char* e = getenv("CMP_ROCTX");
+  if (e && *e && strcmp(e, "0") != 0) {
+    void* h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_GLOBAL);
+    if (!h) h = dlopen("librocprofiler-sdk-roctx.so", RTLD_NOW | RTLD_GLOBAL);
+    if (h) {
+      g_roctx_push = (roctx_push_fn)dlsym(h, "roctxRangePushA");
+      g_roctx_pop = (roctx_pop_fn)dlsym(h, "roctxRangePop");
+      v = g_roctx_push && g_roctx_pop ? 1 : 0;
+    }
+    log_plan("roctx ranges %s", v ? "on" : "requested, but the roctx library was not found");
+  }
+  g_roctx.store(v, std::memory_order_release);
+  return v == 1;
+}
+
+ApiRange::ApiRange(const char* name) : on_(roctx_on()) {
+  if (on_) g_roctx_push(name);
+}
+ApiRange::~ApiRange() {
+  if (on_) g_roctx_pop();
 }
 
 static void push_region(Region* out, int& nreg, int64_t& tiles, int x, int y, int w, int h,

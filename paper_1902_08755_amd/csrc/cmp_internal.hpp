@@ -22,6 +22,23 @@ cmp_status hip_fail(hipError_t e, const char* what);
 bool log_enabled();
 void log_plan(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
 
+// roctx ranges around the entry points: with CMP_ROCTX=1 in the environment
+// (read once per process) each call that enqueues work is one named range on
+// the calling thread (rocprofv3 --marker-trace shows them beside the
+// kernels); the roctx library is loaded on first use, so nothing depends on
+// it otherwise. A range covers the host-side call (validation and enqueue).
+class ApiRange {
+ public:
+  explicit ApiRange(const char* name);
+  ~ApiRange();
+  ApiRange(const ApiRange&) = delete;
+  ApiRange& operator=(const ApiRange&) = delete;
+
+ private:
+  bool on_;
+};
+#define CMP_RANGE(name) ::cmp::ApiRange cmp_api_range_(name)
+
 #define CMP_CHECK_HIP(expr)                                  \
   do {                                                       \
     hipError_t e_ = (expr);                                  \

@@ -138,6 +138,7 @@ extern "C" cmp_status cmp_composite_depth(const cmp_image* in, int32_t n, const 
                                           cmp_rect viewport, uint32_t* out_color,
                                           uint32_t* out_depth, int64_t out_pitch,
                                           cmp_schedule sched, cmp_tile tile, void* stream) {
+  CMP_RANGE("cmp_composite_depth");
   return composite_depth_impl(in, n, roi_dev, false, viewport, out_color, out_depth, out_pitch,
                               sched, tile, stream);
 }
@@ -147,6 +148,7 @@ extern "C" cmp_status cmp_composite_depth_crop(const cmp_image* in, int32_t n,
                                                uint32_t* out_color, uint32_t* out_depth,
                                                int64_t out_pitch, cmp_schedule sched,
                                                cmp_tile tile, void* stream) {
+  CMP_RANGE("cmp_composite_depth_crop");
   CMP_REQUIRE(roi_dev, "roi_dev is required");
   return composite_depth_impl(in, n, roi_dev, true, viewport, out_color, out_depth, out_pitch,
                               sched, tile, stream);

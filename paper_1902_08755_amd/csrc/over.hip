@@ -318,6 +318,7 @@ extern "C" cmp_status cmp_composite_over(const cmp_image* in, int32_t n, cmp_for
                                          const int32_t* order_b2f, cmp_rect viewport,
                                          float* out_rgba, int64_t out_pitch, cmp_schedule sched,
                                          cmp_tile tile, void* stream) {
+  CMP_RANGE("cmp_composite_over");
   cmp_status st = validate_over_inputs(in, n, fmt, order_b2f);
   if (st != CMP_OK) return st;
   CMP_REQUIRE(rect_valid(viewport), "viewport has a negative size");
@@ -402,6 +403,7 @@ extern "C" cmp_status cmp_composite_over_backward(const cmp_image* in, int32_t n
                                                   const int64_t* grad_pitch_layers,
                                                   void* workspace, size_t ws_bytes,
                                                   void* stream) {
+  CMP_RANGE("cmp_composite_over_backward");
   cmp_status st = validate_over_inputs(in, n, fmt, order_b2f);
   if (st != CMP_OK) return st;
   if (n > kBwdMaxLayers) {

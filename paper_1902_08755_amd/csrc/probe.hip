@@ -55,6 +55,7 @@ using namespace cmp;
 
 extern "C" cmp_status cmp_bandwidth_probe(int32_t mode, const void* src, void* dst, size_t bytes,
                                           void* stream) {
+  CMP_RANGE("cmp_bandwidth_probe");
   CMP_REQUIRE(mode == 0 || mode == 1, "mode %d: 0 read, 1 copy", mode);
   CMP_REQUIRE(src && dst && ((uintptr_t)src & 15) == 0 && ((uintptr_t)dst & 15) == 0,
               "src and dst must be 16-byte aligned device pointers");

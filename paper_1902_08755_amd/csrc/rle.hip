@@ -903,6 +903,7 @@ extern "C" cmp_status cmp_rle_compress(const cmp_image* imgs, int32_t n, cmp_for
                                        const uint64_t* capacity, uint64_t* out_size_dev,
                                        int32_t* status_dev, void* workspace, size_t ws_bytes,
                                        void* stream) {
+  CMP_RANGE("cmp_rle_compress");
   CMP_REQUIRE(n >= 0 && n <= kRleMax, "n = %d must be 0..%d", n, kRleMax);
   if (n == 0) return CMP_OK;
   if (fmt != CMP_RGBA8) {
@@ -938,6 +939,7 @@ extern "C" cmp_status cmp_rle_compress_noalloc(const cmp_image* imgs, int32_t n,
                                                uint8_t* const* out, const uint64_t* capacity,
                                                uint64_t* out_size_dev, int32_t* status_dev,
                                                void* stream) {
+  CMP_RANGE("cmp_rle_compress_noalloc");
   CMP_REQUIRE(n >= 0 && n <= kRleMax, "n = %d must be 0..%d", n, kRleMax);
   if (n == 0) return CMP_OK;
   CMP_REQUIRE(imgs, "imgs is NULL");
@@ -1011,6 +1013,7 @@ static cmp_status rle_decompress_impl(const uint8_t* const* in, const uint64_t* 
 extern "C" cmp_status cmp_rle_decompress(const uint8_t* const* in, const uint64_t* in_bytes,
                                          int32_t n, const cmp_image* out, int32_t* roi_out_dev,
                                          int32_t* status_dev, void* stream) {
+  CMP_RANGE("cmp_rle_decompress");
   return rle_decompress_impl(in, in_bytes, n, out, roi_out_dev, status_dev, false, stream);
 }
 
@@ -1018,5 +1021,6 @@ extern "C" cmp_status cmp_rle_decompress_at_roi(const uint8_t* const* in,
                                                 const uint64_t* in_bytes, int32_t n,
                                                 const cmp_image* out, int32_t* roi_out_dev,
                                                 int32_t* status_dev, void* stream) {
+  CMP_RANGE("cmp_rle_decompress_at_roi");
   return rle_decompress_impl(in, in_bytes, n, out, roi_out_dev, status_dev, true, stream);
 }

@@ -568,6 +568,7 @@ extern "C" cmp_status cmp_rle64_compress(const cmp_image* imgs, int32_t n, cmp_f
                                          const uint64_t* capacity, uint64_t* out_size_dev,
                                          int32_t* status_dev, void* workspace, size_t ws_bytes,
                                          void* stream) {
+  CMP_RANGE("cmp_rle64_compress");
   CMP_REQUIRE(n >= 0 && n <= kRleMax, "n = %d must be 0..%d", n, kRleMax);
   if (n == 0) return CMP_OK;
   if (fmt != CMP_RGBA8) {
@@ -592,6 +593,7 @@ extern "C" cmp_status cmp_rle64_compress(const cmp_image* imgs, int32_t n, cmp_f
 extern "C" cmp_status cmp_rle64_decompress(const uint8_t* const* in, const uint64_t* in_bytes,
                                            int32_t n, const cmp_image* out, int32_t* roi_out_dev,
                                            int32_t* status_dev, void* stream) {
+  CMP_RANGE("cmp_rle64_decompress");
   CMP_REQUIRE(n >= 0 && n <= kRleMax, "n = %d must be 0..%d", n, kRleMax);
   if (n == 0) return CMP_OK;
   CMP_REQUIRE(in && in_bytes && out && status_dev, "NULL argument");

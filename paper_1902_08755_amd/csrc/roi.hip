@@ -342,6 +342,7 @@ extern "C" size_t cmp_roi_workspace_size(const cmp_image* imgs, int32_t n) {
 extern "C" cmp_status cmp_roi_detect(const cmp_image* imgs, int32_t n, cmp_format fmt,
                                      int32_t* roi_out_dev, void* workspace, size_t ws_bytes,
                                      void* stream) {
+  CMP_RANGE("cmp_roi_detect");
   CMP_REQUIRE(n >= 0 && n <= kRoiMax, "n = %d must be 0..%d", n, kRoiMax);
   if (n == 0) return CMP_OK;
   CMP_REQUIRE(imgs && roi_out_dev && workspace, "NULL argument");
@@ -403,6 +404,7 @@ extern "C" cmp_status cmp_roi_detect(const cmp_image* imgs, int32_t n, cmp_forma
 extern "C" cmp_status cmp_roi_grid(const cmp_image* imgs, int32_t n, cmp_format fmt,
                                    int32_t cell_w, int32_t cell_h, uint8_t* grid_dev,
                                    void* stream) {
+  CMP_RANGE("cmp_roi_grid");
   CMP_REQUIRE(n >= 0 && n <= kRoiMax, "n = %d must be 0..%d", n, kRoiMax);
   if (n == 0) return CMP_OK;
   CMP_REQUIRE(imgs && grid_dev, "NULL argument");
@@ -573,6 +575,7 @@ __global__ __launch_bounds__(kWave) void roi_rects_kernel(const RectArgs a) {
 extern "C" cmp_status cmp_roi_rects(const cmp_image* imgs, int32_t n, int32_t cell_w,
                                     int32_t cell_h, const uint8_t* grid_dev, int32_t max_rects,
                                     int32_t* rects_dev, int32_t* count_dev, void* stream) {
+  CMP_RANGE("cmp_roi_rects");
   using namespace cmp;
   CMP_REQUIRE(n >= 0 && n <= kRoiMax, "n = %d must be 0..%d", n, kRoiMax);
   if (n == 0) return CMP_OK;

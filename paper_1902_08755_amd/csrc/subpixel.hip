@@ -168,6 +168,7 @@ using namespace cmp;
 extern "C" cmp_status cmp_composite_average(const cmp_image* in, int32_t n, cmp_rect viewport,
                                             uint32_t* out, int64_t out_pitch, cmp_schedule sched,
                                             cmp_tile tile, void* stream) {
+  CMP_RANGE("cmp_composite_average");
   CMP_REQUIRE(n >= 0 && n <= kAvgMax, "n = %d must be 0..%d", n, kAvgMax);
   CMP_REQUIRE(n == 0 || in, "in is NULL");
   for (int i = 0; i < n; ++i) {
@@ -213,6 +214,7 @@ extern "C" cmp_status cmp_composite_average(const cmp_image* in, int32_t n, cmp_
 extern "C" cmp_status cmp_assemble_pixels(const cmp_image* in, int32_t n, const int32_t* offsets,
                                           int32_t kx, int32_t ky, cmp_rect viewport,
                                           uint32_t* out, int64_t out_pitch, void* stream) {
+  CMP_RANGE("cmp_assemble_pixels");
   CMP_REQUIRE(n >= 0 && n <= kAsmMax, "n = %d must be 0..%d", n, kAsmMax);
   CMP_REQUIRE(kx >= 1 && ky >= 1 && kx * ky <= kAsmMax, "pixel kernel %dx%d: 1..64 classes", kx,
               ky);

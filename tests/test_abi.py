@@ -273,3 +273,28 @@ def test_autotune_without_cache_path_or_env_is_rejected():
     finally:
         if saved is not None:
             os.environ["CMP_TUNE_CACHE"] = saved
+
+
+def test_cmp_roctx_loads_ranges_only_when_asked():
+    # CMP_ROCTX=1: the first entry point that enqueues work loads the roctx
+    # library (CMP_LOG reports it) and opens a range; the call itself behaves
+    # as without it (here: rejected on the host)
+    import subprocess
+    import sys
+    code = ("import paper_1902_08755_amd as cmp; L = cmp.lib(); "
+            "st = L.cmp_composite_depth(None, 2, None, cmp.Rect(0, 0, 8, 8), None, None, 8, "
+            "cmp.Schedule(cmp.SEQ, 1), cmp.Tile(0, 0), None); "
+            "assert st == cmp.CMP_EINVAL, st; "
+            "st = L.cmp_composite_depth(None, 2, None, cmp.Rect(0, 0, 8, 8), None, None, 8, "
+            "cmp.Schedule(cmp.SEQ, 1), cmp.Tile(0, 0), None); "
+            "assert st == cmp.CMP_EINVAL, st")
+    env = dict(os.environ, CMP_ROCTX="1", CMP_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    lines = [l for l in r.stderr.splitlines() if l.startswith("[cmp] roctx")]
+    assert lines == ["[cmp] roctx ranges on"], r.stderr
+    env.pop("CMP_ROCTX")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 0 and "roctx" not in r.stderr, r.stderr
