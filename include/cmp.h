@@ -36,6 +36,10 @@
  *    as one "[cmp] ..." line. Read once per process.
  *  - CMP_TUNE_CACHE=<path>: the tune cache that cmp_batch_plan_create and
  *    cmp_autotune use when their path argument is NULL.
+ *  - CMP_ROCTX=1: every call that enqueues work is one roctx range, named
+ *    after the entry point, around its host side (validation and enqueue);
+ *    the roctx library is loaded at the first such call. Read once per
+ *    process.
  */
 #ifndef CMP_H
 #define CMP_H
