@@ -572,8 +572,9 @@ def main():
                     "or an extra: over_fp32, over_fp16, over_backward, batch, rle64) repeatedly")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              "(the multi-GPU design is described, not run)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the library runs the whole path on one GPU; how it would shard is a design "
+              "only)", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)

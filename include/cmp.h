@@ -56,7 +56,7 @@ typedef int32_t cmp_status;
 #define CMP_EINVAL       -1   /* an argument is invalid                        */
 #define CMP_ENOSPC       -2   /* an output or workspace is too small           */
 #define CMP_EHIP         -3   /* the HIP runtime reported an error             */
-#define CMP_EUNSUPPORTED -4   /* a valid request this build does not handle    */
+#define CMP_EUNSUPPORTED -4   /* a valid request the library does not handle   */
 #define CMP_ECORRUPT     -5   /* an RLE stream is malformed (device status)    */
 #define CMP_ETIMEOUT     -6   /* a bounded device-side wait gave up (status)   */
 
