@@ -335,16 +335,33 @@ def batch_jobs(seed=5, njobs=256, device="cpu", log2_range=(6.0, 11.0), n_range=
             for i in range(n):
                 roi, d0, gx, gy = _job_roi(HostRng(jseed, i), w, h)
                 c, d = ramp_block(jseed, i, i, roi, d0, gx, gy, device)
-                imgs.append(DepthImage(_to_i32(c).contiguous(), _to_i32(d).contiguous(), roi))
+                imgs.append(DepthImage(_line_aligned(_to_i32(c), roi[0], 32),
+                                       _line_aligned(_to_i32(d), roi[0], 32), roi))
             jobs.append(Job("depth", DepthWorkload((0, 0, w, h), imgs, f"job{j}")))
         else:
             lay = []
             for i in range(n):
                 roi, _, _, _ = _job_roi(HostRng(jseed, i), w, h)
-                lay.append(OverLayer(brick_layer(jseed, i, roi[2], roi[3], device), roi))
+                layer = brick_layer(jseed, i, roi[2], roi[3], device)[:, :roi[2]]
+                lay.append(OverLayer(_line_aligned(layer, roi[0], 8), roi))
             order = HostRng(jseed, 10_000).permutation(n)
             jobs.append(Job("over", OverWorkload((0, 0, w, h), lay, order, f"job{j}")))
     return jobs
+
+
+def _line_aligned(block: torch.Tensor, x0: int, px_per_line: int) -> torch.Tensor:
+    """The (h, w[, 4]) block as a view into a zeroed buffer whose pitch is a
+    multiple of one 128-byte line (px_per_line pixels), the block starting at
+    column x0 mod px_per_line: a row segment of the block then sits on the same
+    line boundaries as the destination columns it lands on, so a wave's row
+    access touches whole lines (the layout the frames placed at their ROIs
+    have). The pixel values are those of the block."""
+    h, w = block.shape[0], block.shape[1]
+    off = x0 % px_per_line
+    pitch = -(-(off + w) // px_per_line) * px_per_line
+    buf = torch.zeros((h, pitch) + tuple(block.shape[2:]), dtype=block.dtype, device=block.device)
+    buf[:, off:off + w] = block
+    return buf[:, off:off + w]
 
 
 def _job_roi(rng: HostRng, W, H):
