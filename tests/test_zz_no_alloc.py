@@ -57,3 +57,29 @@ def test_noalloc_compress_matches_workspace_path_twice():
     print("noalloc: first input again", flush=True)
     _compare(wl.images, roi, swizzle=False)
 
+
+
+def test_noalloc_at_its_maximum_size():
+    """64 whole images of 3840x2160: 129,600 blocks of 4096 pixels, the most
+    that fit the scratch's 131,072 look-back flags in whole images of that
+    size. The no-allocation call gives the workspace path's streams, and they
+    decode to the images."""
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    print("noalloc: 64 x 3840x2160 ramps, whole images", flush=True)
+    wl = synth.depth_ramps_full(seed=9, n=64, W=3840, H=2160, device=dev)
+    L = cmp.lib()
+    scratch_bytes = 8192 + 256 + 8 * 131072   # CMP_RLE_SCRATCH_BYTES in cmp.h
+    assert L.cmp_rle_workspace_size(cmp._images(wl.images, "u32"), 64) <= scratch_bytes
+    _compare(wl.images, None, swizzle=False)
+    streams, sizes, st = cmp.rle_compress(wl.images)
+    outs = [cmp.Image(torch.zeros_like(im.color), torch.zeros_like(im.depth), im.roi)
+            for im in wl.images]
+    ro, dst = cmp.rle_decompress(streams, outs)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0 and int(dst.abs().sum()) == 0
+    for im, o in zip(wl.images, outs):
+        assert torch.equal(o.color[:, :3840], im.color[:, :3840])
+        assert torch.equal(o.depth[:, :3840], im.depth[:, :3840])
+    del wl, outs, streams
+    torch.cuda.empty_cache()
