@@ -74,12 +74,13 @@ def _random_depth_images(rng, n, W, H, depth_range, device=DEV):
     return imgs
 
 
-@pytest.mark.parametrize("seed", range(10))
+@pytest.mark.parametrize("seed", range(12))
 def test_depth_random_ragged(seed):
     """Random placements (partly outside), pitches, ties, ragged tiles and
-    viewport offsets; 3..60 contributors (more than one pass above 48)."""
+    viewport offsets; 0..150 contributors (more than one pass above 48: up
+    to four)."""
     rng = np.random.default_rng(seed)
-    n = [3, 5, 9, 17, 33, 49, 60, 2, 1, 0][seed]
+    n = [3, 5, 9, 17, 33, 49, 60, 2, 1, 0, 97, 150][seed]
     W, H = int(rng.integers(1, 300)), int(rng.integers(1, 130))
     imgs = _random_depth_images(rng, n, W, H, depth_range=5 if seed % 2 else 2 ** 32 - 1)
     vp = (int(rng.integers(-5, 6)), int(rng.integers(-5, 6)), W, H)
@@ -775,6 +776,35 @@ def test_batch_tune_cache_tiles_do_not_change_results(tmp_path):
     for p in (plan_d, plan_t, plan_l):
         L.cmp_batch_plan_destroy(p)
     del keep_d, keep_t, keep_l
+
+
+def test_batch_many_contributors():
+    """Batched jobs past the 64 a workgroup stages at once: depth jobs of
+    65..130 contributors (staged in chunks of 64, later chunks combined with
+    the output of earlier ones) and over jobs of 65..130 layers (descriptors
+    read from the workspace): the persistent launch equals one plain launch
+    per job, and every job matches the oracle."""
+    import ctypes
+    jobs = synth.batch_jobs(seed=12, njobs=6, device=DEV, log2_range=(5.0, 7.5), n_range=(65, 130))
+    assert min(len(j.work.images if j.kind == "depth" else j.work.layers) for j in jobs) >= 65
+    outs_p, outs_l = _alloc_outs(jobs), _alloc_outs(jobs)
+    arr_p, keep_p = _cjobs(jobs, outs_p)
+    arr_l, keep_l = _cjobs(jobs, outs_l)
+    L = cmp.lib()
+    s = torch.cuda.current_stream().cuda_stream
+    plan_p, plan_l = _plan(L, arr_p, len(jobs), None), _plan(L, arr_l, len(jobs), None)
+    ws = torch.zeros(L.cmp_batch_workspace_size(plan_p) + 64, dtype=torch.uint8, device=DEV)
+    note("batch, 65..130 contributors per job")
+    assert L.cmp_batch_upload(plan_p, ws.data_ptr(), ws.numel(), s) == 0
+    assert L.cmp_batch_run(plan_p, ws.data_ptr(), s) == 0
+    assert L.cmp_batch_run_plain(plan_l, s) == 0
+    torch.cuda.synchronize()
+    for k, job in enumerate(jobs):
+        assert _same(outs_p[k], outs_l[k]), k
+        assert _job_check_oracle(job, outs_p[k]), k
+    for p in (plan_p, plan_l):
+        L.cmp_batch_plan_destroy(p)
+    del keep_p, keep_l
 
 
 def test_batch_plan_reads_tune_cache_from_environment(tmp_path):
