@@ -437,6 +437,77 @@ def read_error_summary(path):
     return out
 
 
+def bench_next_rows(frames, s_obj, reps=50):
+    """The rows built beyond the hot path, on the 16 x 1920x1080 frames, each
+    kernel launched `reps` times back to back over the buffer copies between
+    two events: subpixel compositing (Section 4.2.3: the per-channel mean of
+    the 16 colour frames), pixel-compound assembly (Section 4.2.2: 4 x 4
+    sources of 480x270 interleaved into one 1920x1080 frame) and ROI with
+    holes (Section 5.3: the 64x64-cell occupancy grids of the 16 depth frames,
+    then their rectangles). Outputs are checked equal across the copies."""
+    L = cmp.lib()
+    s = s_obj.cuda_stream
+    W, H, kx, ky, cell = 1920, 1080, 4, 4, 64
+    vp = cmp._rect((0, 0, W, H))
+    seq = cmp.Schedule(cmp.SEQ, 1)
+    gh, gw = -(-H // cell), -(-W // cell)
+    offs = (ctypes.c_int32 * 32)(*[v for i in range(16) for v in (i % kx, i // kx)])
+    per = []
+    for f in frames:
+        dev = f.out_c.device
+        colour = cmp._images([cmp.Image(im.color, None, (0, 0, W, H)) for im in f.images], "u32")
+        srcs = cmp._images([cmp.Image(im.color[:H // ky, :W // kx], None, (0, 0, W // kx, H // ky))
+                            for im in f.images], "u32")
+        grid = torch.zeros(16 * gh * gw, dtype=torch.uint8, device=dev)
+        rects = torch.zeros((16, 4, 4), dtype=torch.int32, device=dev)
+        counts = torch.zeros(16, dtype=torch.int32, device=dev)
+        per.append((f, colour, srcs, torch.empty((H, W), dtype=torch.int32, device=dev),
+                    torch.empty((H, W), dtype=torch.int32, device=dev), grid, rects, counts))
+
+    def average(p):
+        st = L.cmp_composite_average(p[1], 16, vp, p[3].data_ptr(), W, seq, cmp.Tile(0, 0), s)
+        assert st == 0, L.cmp_last_error().decode()
+
+    def assemble(p):
+        st = L.cmp_assemble_pixels(p[2], 16, offs, kx, ky, vp, p[4].data_ptr(), W, s)
+        assert st == 0, L.cmp_last_error().decode()
+
+    def grid(p):
+        st = L.cmp_roi_grid(p[0].img_arr, 16, cmp.RGBA8, cell, cell, p[5].data_ptr(), s)
+        assert st == 0, L.cmp_last_error().decode()
+
+    def rects(p):
+        st = L.cmp_roi_rects(p[0].img_arr, 16, cell, cell, p[5].data_ptr(), 4, p[6].data_ptr(),
+                             p[7].data_ptr(), s)
+        assert st == 0, L.cmp_last_error().decode()
+
+    px = W * H
+    nbytes = {"subpixel_average": 16 * 4 * px + 4 * px, "pixel_assembly": 4 * px + 4 * px,
+              "roi_grid": 16 * 4 * px + 16 * gh * gw, "roi_rects": 16 * gh * gw}
+    res = {}
+    for name, fn in (("subpixel_average", average), ("pixel_assembly", assemble),
+                     ("roi_grid", grid), ("roi_rects", rects)):
+        for p in per:
+            fn(p)
+        torch.cuda.synchronize()
+        t0, t1 = DevEvent(), DevEvent()
+        t0.record(s)
+        for i in range(reps):
+            fn(per[i % len(per)])
+        t1.record(s)
+        torch.cuda.synchronize()
+        us = t0.elapsed_ms(t1) / reps * 1e3
+        res[name] = {"us": us, "bytes": nbytes[name], "GBps": nbytes[name] / us / 1e3,
+                     "hbm_frac": nbytes[name] / us / 1e3 / PEAK_HBM_GBPS}
+    for p in per[1:]:   # every copy holds the same frames
+        assert torch.equal(p[3], per[0][3]) and torch.equal(p[4], per[0][4])
+        assert torch.equal(p[5], per[0][5]) and torch.equal(p[6], per[0][6])
+    res["workloads"] = ("subpixel: mean of 16 colour frames 1920x1080; assembly: 4x4 sources of "
+                        "480x270 into 1920x1080; roi_grid: 64x64 cells of 16 depth frames "
+                        "1920x1080; roi_rects: up to 4 rectangles per frame from those grids")
+    return res
+
+
 def bench_backward(dev, reps=10, which=("forward", "backward", "forward_backward")):
     ow = synth.over_bricks(seed=4, n=32, W=1024, H=1024, device=dev, with_target=True)
     imgs = ow.layers
@@ -569,7 +640,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default="", help="profile helper: run only this stage (or probe_copy, a 1 GiB copy; "
-                    "or an extra: over_fp32, over_fp16, over_backward, batch, rle64) repeatedly")
+                    "or an extra: over_fp32, over_fp16, over_backward, batch, rle64, next_rows) repeatedly")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -633,6 +704,12 @@ def main():
         # profile helper: the RL64 kernels, `steps` launches each
         r = bench_codecs(frames, s_obj, reps=args.steps)
         log(f"ran rl64 compress and decompress {args.steps} times each")
+        print(json.dumps({"only": args.only, **r}))
+        return
+    if args.only == "next_rows":
+        # profile helper: subpixel, assembly, ROI grid and rectangles, `steps` launches each
+        r = bench_next_rows(frames, s_obj, reps=args.steps)
+        log(f"ran the subpixel, assembly, ROI grid and rectangle kernels {args.steps} times each")
         print(json.dumps({"only": args.only, **r}))
         return
     if args.only:
@@ -730,6 +807,7 @@ def main():
         ex["batch_256_jobs"] = bench_batch(dev, tune_path=os.path.join(
             os.environ.get("TMPDIR", "/tmp"), "cmp_tune_cache.txt"))
         ex["codecs_16x1920x1080"] = bench_codecs(frames, s_obj)
+        ex["next_rows_16x1920x1080"] = bench_next_rows(frames, s_obj)
         err = read_error_summary(os.path.join(ROOT, "profiles", "over_error_64x3840x2160.txt"))
         if err:
             ex["over_fp32_64x3840x2160"]["rel_err"] = {k[5:]: v for k, v in err.items() if k.startswith("fp32_")}

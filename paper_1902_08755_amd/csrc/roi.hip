@@ -262,10 +262,14 @@ static int roi_bpp(cmp_format fmt) { return fmt == CMP_RGBA32F ? 16 : fmt == CMP
 // ---------------------------------------------------------------- holes
 // Occupancy of cw x ch cells (Section 5.3: analysing the framebuffer also
 // finds holes in the rendered area). A workgroup scans the rows of one cell
-// row and a chunk of whole cells (so each cell has one writer), one pixel
-// per lane per load, kRoiBatch loads in flight; data pixels set their
-// cell's byte flag in LDS, and the flags are written out at the end.
+// row and a chunk of whole cells about kGridChunkCols columns wide (so each
+// cell has one writer). Lane = column: each thread walks its column down the
+// cell row, kRoiBatch rows of loads in flight (every wave access one
+// coalesced row segment), and ORs whether any of its pixels holds data; a
+// thread that saw data sets its cell's byte flag in LDS once, and the flags
+// are written out at the end.
 constexpr int kGridChunkCells = 1024;   // LDS flags per workgroup
+constexpr int kGridChunkCols = 256;     // columns of a chunk (one per thread)
 
 struct GridImg {
   const void* data;
@@ -302,27 +306,25 @@ __global__ __launch_bounds__(kThreads) void roi_grid_kernel(const GridArgs a) {
   const int y0 = band * a.ch, y1 = min(I.h, y0 + a.ch);
   for (int k = threadIdx.x; k < ncells; k += kThreads) flags[k] = 0;
   __syncthreads();
-  const int cols = x1 - x0;
-  const int work = cols * (y1 - y0);
-  const uint8_t* base = reinterpret_cast<const uint8_t*>(I.data);
-  for (int t0 = threadIdx.x; t0 < work; t0 += kThreads * kRoiBatch) {
-    uint32_t m[kRoiBatch];
-    int xs[kRoiBatch];
+  const int rows = y1 - y0;
+  const int64_t row_bytes = I.pitch * bpp;
+  const uint8_t* base = reinterpret_cast<const uint8_t*>(I.data) + (int64_t)y0 * row_bytes;
+  for (int x = x0 + (int)threadIdx.x; x < x1; x += kThreads) {
+    uint32_t any = 0;
+    for (int r0 = 0; r0 < rows; r0 += kRoiBatch) {
+      uint32_t m[kRoiBatch];
 #pragma unroll
-    for (int k = 0; k < kRoiBatch; ++k) {
-      // unconditional load (an index past the end reads the first pixel of
-      // the chunk and is ignored), so that the batch is in flight together
-      const int t = t0 + k * kThreads;
-      const bool ok = t < work;
-      const int tc = ok ? t : 0;
-      const int ry = tc / cols, x = x0 + (tc - ry * cols);
-      xs[k] = x;
-      const uint32_t mm = px_mask<MODE>(base + (int64_t)(y0 + ry) * I.pitch * bpp, x);
-      m[k] = ok ? mm : 0u;
+      for (int k = 0; k < kRoiBatch; ++k) {
+        // unconditional loads (a row past the band's end reads its first row
+        // and is ignored), so that the batch is in flight together
+        const int r = r0 + k < rows ? r0 + k : 0;
+        m[k] = px_mask<MODE>(base + r * row_bytes, x);
+      }
+#pragma unroll
+      for (int k = 0; k < kRoiBatch; ++k)
+        if (r0 + k < rows) any |= m[k];
     }
-#pragma unroll
-    for (int k = 0; k < kRoiBatch; ++k)
-      if (m[k]) flags[(xs[k] - x0) / a.cw] = 1;   // every writer stores the same value
+    if (any) flags[(x - x0) / a.cw] = 1;   // every writer stores the same value
   }
   __syncthreads();
   uint8_t* g = a.grid + I.grid_off + (int64_t)band * I.gw + c0;
@@ -423,8 +425,11 @@ extern "C" cmp_status cmp_roi_grid(const cmp_image* imgs, int32_t n, cmp_format 
   memset(&a, 0, sizeof a);
   a.cw = cell_w;
   a.ch = cell_h;
-  a.chunk_cells = kGridChunkCells;
-  if ((int64_t)a.chunk_cells * cell_w > 4096) a.chunk_cells = 4096 / cell_w > 0 ? 4096 / cell_w : 1;
+  // chunks of whole cells about kGridChunkCols columns wide (one column per
+  // thread, enough workgroups to fill the device), wider for short cells so
+  // that a workgroup still scans about 16K pixels
+  const int chunk_cols = std::max(kGridChunkCols, 16384 / cell_h);
+  a.chunk_cells = std::min(kGridChunkCells, std::max(1, chunk_cols / cell_w));
   int64_t wg = 0, goff = 0;
   for (int i = 0; i < n; ++i) {
     const cmp_image& I = imgs[i];
